@@ -1,0 +1,28 @@
+"""FP64 CPU oracle for the direction-dependent calibration hot path.
+
+TEST INFRASTRUCTURE ONLY.  Nothing on the product path imports, calls or links this
+package: only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may use it.  It shares no code with the HIP library; both sides read the same
+seeded draws from :mod:`paper_1910_13908_amd.synth`, which holds no calibration arithmetic.
+
+What it computes (NumPy, float64 / complex128 throughout):
+
+* ``rime``     - the model-coherency predict, the per-visibility model J_p C J_q^H, the
+                 residual and the cost (plain definitions).
+* ``normal_eq``- the 8N x 8N Gauss-Newton normal equations built by brute force from an
+                 explicit per-visibility Jacobian (plain definition).
+* ``lm``       - Levenberg-Marquardt for one cluster and the SAGE sweep over clusters
+                 (iterations, written step by step).
+* ``align``    - unitary (Procrustes) alignment used to compare gains.
+* ``adjoint``  - gradient of the cost with respect to every cluster's Jones matrices.
+
+The paper (Sections 2 and 3) fixes only the problem dimensions: N stations, N(N-1)/2
+baselines, sources grouped into clusters with one calibration solution per cluster.
+Everything else follows the textbook radio-interferometric measurement equation
+(Hamaker, Bregman & Sault 1996) and Levenberg-Marquardt as in Madsen, Nielsen & Tingleff
+(2004), Algorithm 3.16; the readings taken where both are silent are listed in the design doc.
+
+Parity status: every function here is pinned by ``tests/test_oracle_*.py`` (closed forms,
+invariants, finite differences, brute force at tiny sizes, exact recovery, chi-square
+bound).  The whole N=512 run has no closed form beyond those invariants.
+"""

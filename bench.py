@@ -1,0 +1,191 @@
+#!/usr/bin/env python3
+"""Benchmark of the calibration hot path on one MI355X.
+
+One step = one full calibration of the N=512 (SKA1-LOW scale) workload through the C ABI:
+predict of all 20 clusters x 50 sources, then 3 SAGE sweeps x 20 clusters x 10 LM
+iterations (600 LM iterations, each: normal-equation build over 1,308,160 visibilities,
+4096 x 4096 damped Cholesky, triangular solves, FP64 refinement, trial cost, accept/reject).
+Inputs (uvw, sky, noisy visibilities) are resident in HBM before the timed region; the Jones
+start from identity at the beginning of every step.
+
+Prints ONE JSON line (metric = LM iterations per second, mixed precision).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp32_mfma_tflops": 157.3, "fp64_mfma_tflops": 78.6, "hbm_gbs": 8000.0}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="n512_k20")
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-compare", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(cfg, seed):
+    """The FP64 oracle on the host: one LM iteration of cluster 0 at full size."""
+    from oracle import rime, normal_eq as ne, lm as olm
+    from paper_1910_13908_amd import synth
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    ob = synth.make_obs(cfg, seed=seed)
+    offs = ob.cluster_offset[:2]
+    t0 = time.perf_counter()
+    C0 = rime.predict(ob.u, ob.v, ob.w, ob.freqs, ob.l, ob.m, ob.I, ob.Q, ob.U, ob.V, offs)[0]
+    t_pred = time.perf_counter() - t0
+    Y = rime.model_cluster(C0, ob.jones_true[0], ob.ant_p, ob.ant_q) + ob.noise
+    J = synth.identity_jones(1, ob.N)[0]
+    t0 = time.perf_counter()
+    H, g, f = ne.normal_equations(Y, C0, J, ob.ant_p, ob.ant_q)
+    mu = 1e-3 * float(np.max(np.diag(H)))
+    mu_eff = max(mu, 1e-6 * float(np.max(np.diag(H))))
+    d = olm.damped_solve(H, g, mu_eff)
+    f_new = rime.cost(Y - rime.model_cluster(C0, ne.unpack_jones(ne.pack_jones(J) + d), ob.ant_p, ob.ant_q))
+    t_iter = time.perf_counter() - t0
+    vis = ob.B * ob.T * ob.F
+    return {
+        "value": 1.0 / t_iter, "unit": "LM iters/s", "cores": int(threads), "kind": "oracle",
+        "sample": (f"one FP64 LM iteration of cluster 0 at N={ob.N} (8N={8 * ob.N}): brute-force "
+                   f"normal equations over {vis} visibilities, LAPACK Cholesky solve, trial cost; "
+                   f"{t_iter:.1f} s"),
+        "predict_gvis_per_s": vis / t_pred / 1e9,
+        "predict_sample": f"predict of cluster 0 ({ob.cluster_offset[1]} sources): {t_pred:.1f} s",
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU layout is "
+              "described in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1910_13908_amd import synth, ddcal as dd
+
+    cfg = synth.CONFIGS[args.config]
+    prec = dd.MIXED if args.precision == "mixed" else dd.FP64
+    dt = torch.float32 if prec == dd.MIXED else torch.float64
+    ob = synth.make_obs(cfg, seed=args.seed)
+    ctx = dd.Context(0)
+    obs = dd.device_obs(ob)
+    sky = dd.device_sky(ob)
+    K, N = ob.K, ob.N
+
+    def make_vis(p, dtype):
+        noise = torch.as_tensor(dd.planes(ob.noise), dtype=dtype, device="cuda").contiguous()
+        coh = ctx.predict(obs, sky, p)
+        Jt = torch.as_tensor(dd.jones_real(ob.jones_true), device="cuda").contiguous()
+        V = torch.empty_like(noise)
+        ctx.add_model(obs, K, noise, coh, Jt, 1.0, p, V)
+        del coh, noise
+        torch.cuda.synchronize()
+        return V
+
+    V = make_vis(prec, dt)
+    J0 = torch.as_tensor(dd.jones_real(synth.identity_jones(K, N)), device="cuda").contiguous()
+    J = J0.clone()
+    lm = dd.default_lm_opts(n_iter=cfg.n_lm, precision=prec)
+    n_lm_per_step = cfg.n_sweeps * K * cfg.n_lm
+
+    def step(want_info=False):
+        J.copy_(J0)
+        return ctx.calibrate(obs, sky, V, J, cfg.n_sweeps, lm, want_info=want_info)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.enable_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    timers = {name: ctx.timing(i) for i, name in enumerate(
+        ["cholesky", "predict", "build", "trsv", "trial", "model", "refine"])}
+    ctx.enable_timing(False)
+    infos = step(want_info=True)
+    torch.cuda.synchronize()
+    final_cost = sum(i.cost for i in infos[-1]) if infos else None
+
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = n_lm_per_step * args.steps / elapsed
+    n_ch, ms_ch, fl_ch = timers["cholesky"]
+    peak = PEAK["fp32_mfma_tflops"] if prec == dd.MIXED else PEAK["fp64_mfma_tflops"]
+    achieved = fl_ch / (ms_ch * 1e-3) / 1e12 if ms_ch > 0 else 0.0
+    n_pr, ms_pr, terms = timers["predict"]
+    vis_per_predict = K * ob.B * ob.T * ob.F
+    gvis = (n_pr * vis_per_predict) / (ms_pr * 1e-3) / 1e9 if ms_pr > 0 else 0.0
+    kernel_ms = {k: {"launches": v[0], "avg_us": 1e3 * v[1] / max(v[0], 1),
+                     "share_of_step": v[1] / (1e3 * elapsed) if elapsed > 0 else 0.0}
+                 for k, v in timers.items()}
+    nb, msb, byb = timers["build"]
+
+    out = {
+        "metric": "LM iters/s", "value": value, "unit": "LM iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if prec == dd.MIXED else "f64",
+        "data": "synthetic (seeded generator; the paper's data sets are not available)",
+        "config": {"workload": f"{args.config}: N={N} stations, B={ob.B} baselines, K={K} clusters x "
+                               f"{cfg.sources_per_cluster} sources, T={ob.T}, F={ob.F}, "
+                               f"{cfg.n_sweeps} SAGE sweeps x {cfg.n_lm} LM iterations, "
+                               f"{'mixed' if prec == dd.MIXED else 'fp64'} precision",
+                   "n_stations": N, "n_clusters": K, "lm_iters_per_step": n_lm_per_step,
+                   "precision": args.precision},
+        "roofline": {"bound": "mfma", "kernel": "k_cholesky", "achieved": achieved, "peak": peak,
+                     "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": None,
+                     "per_launch": f"(8N)^3/3 = {(8 * N) ** 3 / 3:.3e} flop per factorisation, "
+                                   f"avg {1e3 * ms_ch / max(n_ch, 1):.1f} us over {n_ch} launches"},
+        "predict_gvis_per_s": gvis,
+        "predict_gterms_per_s": terms / (ms_pr * 1e-3) / 1e9 if ms_pr > 0 else 0.0,
+        "build_gbs": byb / (msb * 1e-3) / 1e9 if msb > 0 else 0.0,
+        "kernels": kernel_ms,
+        "final_total_cost": final_cost,
+    }
+
+    if prec == dd.MIXED and not args.no_fp64_compare:
+        del V
+        torch.cuda.empty_cache()
+        V64 = make_vis(dd.FP64, torch.float64)
+        J64 = J0.clone()
+        lm64 = dd.default_lm_opts(n_iter=cfg.n_lm, precision=dd.FP64)
+        ctx.calibrate(obs, sky, V64, J64, cfg.n_sweeps, lm64, want_info=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        J64.copy_(J0)
+        ctx.calibrate(obs, sky, V64, J64, cfg.n_sweeps, lm64, want_info=False)
+        torch.cuda.synchronize()
+        out["fp64_path_lm_iters_per_s"] = n_lm_per_step / (time.perf_counter() - t0)
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, args.seed)
+
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,123 @@
+// Internal declarations shared by the HIP sources of libddcal (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ddc {
+
+constexpr double kCLight = 299792458.0;
+
+// Tile edge of the blocked Cholesky and of the triangular solves.
+constexpr int NB = 64;
+
+// Number of per-baseline partial sums written by the normal-equation build:
+// P (4: P00, P11, Re P01, Im P01), zl (8), Q (4), zr (8).
+constexpr int kPartials = 24;
+
+// Device-side state of one Levenberg-Marquardt solve (FP64 throughout).
+struct LMState {
+  double mu, nu;          // damping and its growth factor
+  double mu_eff;          // damping used in the current iteration
+  double f;               // cost at the current Jones
+  double f0;              // cost at the starting Jones
+  double f_trial;         // cost at the trial Jones
+  double g_norm2;         // ||g||^2 of the current right-hand side (refinement stop test)
+  double maxdiag;         // max diag of the current normal matrix
+  int32_t need_build;     // 1: rebuild H, g, f at the current Jones
+  int32_t fresh;          // 1: initialise mu from tau at the next build
+  int32_t notpd;          // factorisation of the current iteration failed
+  int32_t refine_done;    // refinement converged (or not requested) this iteration
+  int32_t refine_steps;   // refinement steps taken this iteration
+  int32_t max_refine;     // max over iterations
+  int32_t n_accept, n_reject, n_notpd;
+  int32_t timeout;        // an inter-workgroup wait exceeded its bound
+  int32_t iter;           // iterations done
+  int32_t pad;
+};
+
+// Scratch for the persistent kernels: ticket counters, exit counter and per-tile flags.
+struct SyncArea {
+  uint32_t ticket;
+  uint32_t exited;
+  uint32_t abort;
+  uint32_t pad;
+};
+
+}  // namespace ddc
+
+// ---------------------------------------------------------------------------------------
+// Kernel launchers (defined in the .hip files; all enqueue on `st`).
+// ---------------------------------------------------------------------------------------
+namespace ddc {
+
+struct ObsDev {
+  int N, T, F;
+  int64_t B;
+  const double* u;
+  const double* v;
+  const double* w;
+  const double* freq;
+  const int32_t* ant_p;   // canonical baseline table, owned by the context
+  const int32_t* ant_q;
+};
+
+// k_predict.hip
+template <typename R>
+hipError_t launch_predict(const ObsDev& o, int K, const int32_t* offs_dev, const int32_t* offs_host,
+                          const double* l, const double* m, const double* I, const double* Q,
+                          const double* U, const double* V, R* coh, hipStream_t st);
+
+// k_vis.hip
+template <typename R>
+hipError_t launch_add_model(const ObsDev& o, int k0, int k1, const R* in, const R* coh,
+                            const double* jones, double alpha, R* out, double* cost_part,
+                            int* nblk, hipStream_t st);
+hipError_t launch_sum(const double* parts, int n, double* out, hipStream_t st);
+template <typename R>
+hipError_t launch_build_neq(const ObsDev& o, const R* y, const R* coh, const double* jones,
+                            R* Hc, int ld, R* part, double* cost_part, int* nblk,
+                            const LMState* lm, hipStream_t st);
+template <typename R>
+hipError_t launch_neq_station(const ObsDev& o, const R* part, R* Hc, int ld, double* g,
+                              double* diag, const LMState* lm, hipStream_t st);
+template <typename R>
+hipError_t launch_trial_cost(const ObsDev& o, const R* y, const R* coh, const double* jones,
+                             const double* d, double* cost_part, int* nblk, const LMState* lm,
+                             hipStream_t st);
+
+// k_chol.hip
+template <typename R>
+hipError_t launch_cholesky(const R* Hc, int ld, int n_pad, const double* mu_dev, double mu_host,
+                           R* Lt, R* Linv, SyncArea* sync, uint32_t* flags, int32_t* status,
+                           const LMState* lm, hipStream_t st, int n_wg);
+template <typename R>
+hipError_t launch_trsv(bool forward, const R* Lt, const R* Linv, int n_pad, const double* b,
+                       double* x, double* acc_out, SyncArea* sync, uint32_t* flags,
+                       int32_t* status, const LMState* lm, int gate, hipStream_t st);
+template <typename R>
+hipError_t launch_refine_resid(const R* Hc, int ld, int n_pad, const double* mu_dev,
+                               const double* g, const double* d, double* s, double* s_part,
+                               const LMState* lm, int gate, hipStream_t st);
+hipError_t set_chol_smem_attr();
+
+// k_lm.hip
+hipError_t launch_lm_init(LMState* st, int fresh, double mu, double nu, hipStream_t s);
+hipError_t launch_lm_pre(LMState* st, const double* cost_part, int nblk, const double* diag,
+                         int n8, const double* g, double tau, double mu_floor, int refine_max,
+                         hipStream_t s);
+hipError_t launch_lm_post(LMState* st, const double* cost_part, int nblk, const double* d,
+                          const double* g, int n8, double* jones, hipStream_t s);
+hipError_t launch_refine_ctrl(LMState* st, const double* s_part, int T, double tol2,
+                              hipStream_t s);
+hipError_t launch_solve_setup(LMState* st, const double* g, int n, double mu, int refine_max,
+                              hipStream_t s);
+hipError_t launch_copy_state(const LMState* st, LMState* dst, hipStream_t s);
+template <typename R>
+hipError_t launch_init_matrix(R* Hc, int ld, int n_real, hipStream_t s);
+template <typename R>
+hipError_t launch_expand_sym(const R* Hc, int ld, int n, R* out, hipStream_t s);
+template <typename Rin, typename Rout>
+hipError_t launch_convert(const Rin* in, int64_t n, int64_t n_out, Rout* out, hipStream_t s);
+
+}  // namespace ddc

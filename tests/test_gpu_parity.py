@@ -1,0 +1,230 @@
+"""GPU path vs the FP64 oracle, element by element, through the C ABI.
+
+Tolerances (from the arithmetic and the stated targets):
+* FP64 path: predict, residual, normal equations within 1e-11 relative (the phase argument
+  alone carries ~1e-12 relative rounding on these baselines); LM/SAGE gains within 1e-8
+  after unitary alignment.  Accept/reject decisions taken when f - f' is at the rounding
+  level of the cost sums are not unique, so LM trajectories are compared by their results
+  (gains, costs), not by their accept counts.
+* Mixed path: 1e-5 relative residual / coherency / normal-matrix error, gains within 1e-4
+  after alignment, cost within 1e-5 relative.
+"""
+import numpy as np
+import pytest
+
+from oracle import rime, normal_eq as ne, lm as olm, align
+from paper_1910_13908_amd import synth
+
+from _gpu_util import setup, to_dev, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dd():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1910_13908_amd import ddcal
+    return ddcal
+
+
+@pytest.fixture(scope="module")
+def ctx(dd):
+    c = dd.Context(0)
+    yield c
+    c.close()
+
+
+SMALL = synth.ObsConfig(13, 3, 5, 3, (140e6, 160e6), jones_amp=0.2)           # B=78, ragged
+POL = synth.ObsConfig(9, 2, 4, 2, (150e6,), polarised=True, jones_amp=0.2)
+WIDE = synth.ObsConfig(40, 1, 300, 2, (150e6,), disk_radius_m=20000.0)        # 300 sources > LDS chunk
+
+
+@pytest.mark.parametrize("cfg", [SMALL, POL, WIDE], ids=["small", "polarised", "wide"])
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
+def test_predict(dd, ctx, cfg, prec):
+    ob, V, C = setup(cfg, seed=1)
+    d = to_dev(dd, ob, prec)
+    coh = ctx.predict(d["obs"], d["sky"], prec).cpu().numpy()
+    got = dd.unplanes(coh)
+    tol = 1e-11 if prec == 0 else 1e-5
+    for k in range(ob.K):
+        assert rel(got[k], C[k]) <= tol, (k, rel(got[k], C[k]))
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
+def test_add_model_and_residual(dd, ctx, prec):
+    import torch
+    ob, V, C = setup(SMALL, seed=2)
+    d = to_dev(dd, ob, prec, noise=ob.noise)
+    coh = ctx.predict(d["obs"], d["sky"], prec)
+    Vg = torch.empty_like(d["noise"])
+    ctx.add_model(d["obs"], ob.K, d["noise"], coh, d["J_true"], +1.0, prec, Vg)
+    tol = 1e-11 if prec == 0 else 1e-5
+    assert rel(dd.unplanes(Vg.cpu().numpy()), V) <= tol
+    # residual at perturbed gains (not the optimum) against the oracle
+    rng = np.random.default_rng(3)
+    J = ob.jones_true + 0.05 * (rng.normal(size=ob.jones_true.shape) + 1j * rng.normal(size=ob.jones_true.shape))
+    Jd = torch.as_tensor(dd.jones_real(J), device="cuda")
+    Vd = torch.as_tensor(dd.planes(V), dtype=d["dt"], device="cuda").contiguous()
+    R = torch.empty_like(Vd)
+    cost = ctx.residual(d["obs"], ob.K, Vd, coh, Jd, prec, R)
+    Ro = rime.residual(V, C, J, ob.ant_p, ob.ant_q)
+    assert np.linalg.norm(dd.unplanes(R.cpu().numpy()) - Ro) <= tol * np.linalg.norm(V)
+    assert abs(cost - rime.cost(Ro)) <= (1e-11 if prec == 0 else 1e-5) * rime.cost(Ro)
+    # cost only (no residual written)
+    cost2 = ctx.residual(d["obs"], ob.K, Vd, coh, Jd, prec, None)
+    assert cost2 == cost
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
+@pytest.mark.parametrize("pol", [False, True], ids=["unpol", "pol"])
+def test_normal_equations(dd, ctx, prec, pol):
+    import torch
+    cfg = synth.ObsConfig(12, 1, 4, 3, (145e6, 155e6), polarised=pol, jones_amp=0.2)  # 8N = 96: padded
+    ob, V, C = setup(cfg, seed=4)
+    d = to_dev(dd, ob, prec)
+    rng = np.random.default_rng(5)
+    J = ob.jones_true[0] + 0.1 * (rng.normal(size=(12, 2, 2)) + 1j * rng.normal(size=(12, 2, 2)))
+    H, g, f = ne.normal_equations(V, C[0], J, ob.ant_p, ob.ant_q)
+    coh = ctx.predict(d["obs"], d["sky"], prec)
+    Y = torch.as_tensor(dd.planes(V), dtype=d["dt"], device="cuda").contiguous()
+    Jd = torch.as_tensor(dd.jones_real(J), device="cuda").contiguous()
+    Hg, gg, fg = ctx.build_normal_eq(d["obs"], Y, coh[0].contiguous(), Jd, prec)
+    Hg = Hg.double().cpu().numpy()
+    gg = gg.double().cpu().numpy()
+    tol = 1e-11 if prec == 0 else 1e-5
+    assert np.array_equal(Hg, Hg.T)
+    assert rel(Hg, H) <= tol, rel(Hg, H)
+    assert rel(gg, g) <= tol, rel(gg, g)
+    assert abs(fg - f) <= tol * f
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
+@pytest.mark.parametrize("n", [8, 64, 100, 512, 1000])
+def test_damped_solve(dd, ctx, prec, n):
+    import torch
+    rng = np.random.default_rng(n)
+    A = rng.normal(size=(n + 10, n))
+    H = A.T @ A
+    g = rng.normal(size=n)
+    mu = 1e-3 * np.max(np.diag(H))
+    dt = torch.float32 if prec == 1 else torch.float64
+    Hd = torch.as_tensor(H, dtype=dt, device="cuda").contiguous()
+    gd = torch.as_tensor(g, dtype=dt, device="cuda").contiguous()
+    d, steps = ctx.damped_solve(Hd, gd, mu, prec, refine_tol=1e-12, refine_max=8)
+    d = d.cpu().numpy()
+    # the system actually solved is the one stored in the precision's element type
+    Hs = Hd.double().cpu().numpy()
+    gs = gd.double().cpu().numpy()
+    M = Hs + mu * np.eye(n)
+    berr = np.linalg.norm(M @ d - gs) / np.linalg.norm(gs)
+    ref = np.linalg.solve(M, gs)
+    if prec == 0:
+        assert berr <= 1e-12, berr
+        assert rel(d, ref) <= 1e-10
+    else:
+        assert berr <= 1e-11, (berr, steps)
+        assert rel(d, ref) <= 1e-9
+        assert steps >= 1
+
+
+def test_damped_solve_not_pd(dd, ctx):
+    import torch
+    H = -np.eye(70)
+    Hd = torch.as_tensor(H, device="cuda").contiguous()
+    gd = torch.ones(70, dtype=torch.float64, device="cuda")
+    with pytest.raises(dd.DdcError) as e:
+        ctx.damped_solve(Hd, gd, 0.0, 0)
+    assert e.value.status == dd.ENOTPD
+
+
+def _lm_problem(dd, prec, cfg=synth.CONFIGS["n64_k1"], seed=0):
+    import torch
+    ob, V, C = setup(cfg, seed=seed)
+    d = to_dev(dd, ob, prec, V=V)
+    return ob, V, C, d
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
+def test_lm_solve_n64(dd, ctx, prec):
+    import torch
+    ob, V, C, d = _lm_problem(dd, prec)
+    J0 = synth.identity_jones(1, ob.N)[0]
+    Jo, io = olm.lm_solve(V, C[0], J0, ob.ant_p, ob.ant_q, n_iter=20)
+    coh = ctx.predict(d["obs"], d["sky"], prec)
+    Jd = torch.as_tensor(dd.jones_real(J0), device="cuda").contiguous()
+    opts = dd.default_lm_opts(n_iter=20, precision=prec)
+    info = ctx.lm_solve(d["obs"], d["V"], coh[0].contiguous(), Jd, opts)
+    Jg = dd.jones_complex(Jd.cpu().numpy())
+    err = align.align_error(Jg, Jo)
+    if prec == 0:
+        assert err <= 1e-8, err
+        assert abs(info.cost - io.cost) <= 1e-9 * io.cost
+        assert abs(info.cost0 - io.cost0) <= 1e-11 * io.cost0
+        # accept counts are not compared: once the decrease f - f' reaches the rounding level
+        # of the cost sums, accept/reject is decided by summation order, on either side.
+    else:
+        assert err <= 1e-4, err
+        assert abs(info.cost - io.cost) <= 1e-5 * io.cost
+    assert info.n_notpd == 0
+
+
+def test_lm_resume_and_determinism(dd, ctx):
+    import torch
+    ob, V, C, d = _lm_problem(dd, 1, cfg=synth.ObsConfig(24, 1, 6, 4, (150e6,)), seed=3)
+    coh = ctx.predict(d["obs"], d["sky"], 1)[0].contiguous()
+    J0 = torch.as_tensor(dd.jones_real(synth.identity_jones(1, ob.N)[0]), device="cuda").contiguous()
+    opts20 = dd.default_lm_opts(n_iter=20, precision=1)
+    opts10 = dd.default_lm_opts(n_iter=10, precision=1)
+    Ja = J0.clone()
+    ia = ctx.lm_solve(d["obs"], d["V"], coh, Ja, opts20)
+    Jb = J0.clone()
+    ctx.lm_solve(d["obs"], d["V"], coh, Jb, opts20)
+    assert torch.equal(Ja, Jb)                       # deterministic, bit for bit
+    Jc = J0.clone()
+    st = dd.LMState(0.0, 0.0, 1)
+    ctx.lm_solve(d["obs"], d["V"], coh, Jc, opts10, st)
+    ic = ctx.lm_solve(d["obs"], d["V"], coh, Jc, opts10, st)
+    assert torch.equal(Ja, Jc)                       # 10 + 10 == 20
+    assert ic.cost == ia.cost
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
+def test_calibrate_sage(dd, ctx, prec):
+    import torch
+    cfg = synth.ObsConfig(20, 3, 5, 4, (145e6, 155e6), jones_amp=0.15)
+    ob, V, C = setup(cfg, seed=6)
+    J0 = synth.identity_jones(3, ob.N)
+    Jo, Ro, io, _ = olm.calibrate(V, C, J0, ob.ant_p, ob.ant_q, n_sweeps=3, n_lm=8)
+    d = to_dev(dd, ob, prec, V=V)
+    Jd = torch.as_tensor(dd.jones_real(J0), device="cuda").contiguous()
+    R = torch.empty_like(d["V"])
+    infos = ctx.calibrate(d["obs"], d["sky"], d["V"], Jd, 3, dd.default_lm_opts(n_iter=8, precision=prec), res=R)
+    Jg = dd.jones_complex(Jd.cpu().numpy())
+    tol_j = 1e-8 if prec == 0 else 1e-4
+    for k in range(3):
+        assert align.align_error(Jg[k], Jo[k]) <= tol_j, (k, align.align_error(Jg[k], Jo[k]))
+    Rg = dd.unplanes(R.cpu().numpy())
+    assert np.linalg.norm(Rg - Ro) <= (1e-11 if prec == 0 else 1e-5) * np.linalg.norm(V)
+    # per-visit costs: an LM visit stopped after 8 iterations sits on its convergence path,
+    # and a step accepted on one side at rounding-level rho puts it one step ahead, so the
+    # FP64 bound is the size of such a late step (1e-8 relative), not the rounding level.
+    for e in range(3):
+        for k in range(3):
+            assert abs(infos[e][k].cost - io[e][k].cost) <= (1e-8 if prec == 0 else 1e-5) * io[e][k].cost
+
+
+def test_invalid_arguments(dd, ctx):
+    import torch
+    ob, V, C, d = _lm_problem(dd, 0, cfg=synth.ObsConfig(5, 1, 2, 2, (150e6,)))
+    bad = dd.Obs(1, 2, 1, d["obs"].c.u, d["obs"].c.v, d["obs"].c.w, d["obs"].c.freq_hz)
+    import ctypes as ct
+    coh = torch.empty((1, 8, 2, 1, 10), dtype=torch.float64, device="cuda")
+    st = dd._lib.ddc_predict(ctx.h, ct.byref(bad), ct.byref(d["sky"].c), 0, coh.data_ptr())
+    assert st == dd.EINVAL
+    st = dd._lib.ddc_predict(ctx.h, ct.byref(d["obs"].c), ct.byref(d["sky"].c), 7, coh.data_ptr())
+    assert st == dd.EINVAL
+    st = dd._lib.ddc_predict(ctx.h, ct.byref(d["obs"].c), None, 0, coh.data_ptr())
+    assert st == dd.EINVAL
+    assert b"sky" in dd._lib.ddc_last_error(ctx.h)

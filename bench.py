@@ -127,7 +127,7 @@ def main():
     ctx.enable_timing(False)
     infos = step(want_info=True)
     torch.cuda.synchronize()
-    final_cost = sum(i.cost for i in infos[-1]) if infos else None
+    final_cost = infos[-1][-1].cost if infos else None   # residual cost after the last visit
 
     ms_per_step = 1e3 * elapsed / args.steps
     value = n_lm_per_step * args.steps / elapsed

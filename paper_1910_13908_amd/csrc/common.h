@@ -87,10 +87,12 @@ hipError_t launch_trial_cost(const ObsDev& o, const R* y, const R* coh, const do
                              hipStream_t st);
 
 // k_chol.hip
+// Factor H + mu I (mu from mu_dev if non-null); with g != null also y = L^{-1} g.
 template <typename R>
 hipError_t launch_cholesky(const R* Hc, int ld, int n_pad, const double* mu_dev, double mu_host,
-                           R* Lt, R* Linv, SyncArea* sync, uint32_t* flags, int32_t* status,
-                           const LMState* lm, hipStream_t st, int n_wg);
+                           const double* g, double* y, R* Lt, R* Linv, SyncArea* sync,
+                           uint32_t* flags, uint32_t* yflags, int32_t* status, hipStream_t st,
+                           int n_wg);
 template <typename R>
 hipError_t launch_trsv(bool forward, const R* Lt, const R* Linv, int n_pad, const double* b,
                        double* x, double* acc_out, SyncArea* sync, uint32_t* flags,

@@ -279,15 +279,12 @@ ddc_status enqueue_solve(ddc_ctx* c, SolveBufs& b, LMState* lm, int refine_max, 
   R* Hc = reinterpret_cast<R*>(b.Hc);
   R* Lt = reinterpret_cast<R*>(b.Lt);
   R* Li = reinterpret_cast<R*>(b.Linv);
+  // the factorisation also runs the forward substitution y = L^{-1} g
   DDCCK(timed(c, T_CHOL, chol_flop(b.n), [&] {
-    return launch_cholesky<R>(Hc, b.ld, b.n_pad, &lm->mu_eff, 0.0, Lt, Li, c->area(0),
-                              c->chol_flags(), &lm->notpd, lm, st, c->chol_wg);
+    return launch_cholesky<R>(Hc, b.ld, b.n_pad, &lm->mu_eff, 0.0, b.g, b.y, Lt, Li, c->area(0),
+                              c->chol_flags(), c->fwd_flags(), &lm->notpd, st, c->chol_wg);
   }));
   const double tri_bytes = (double)b.n_pad * (b.n_pad + 64) / 2 * sizeof(R);
-  DDCCK(timed(c, T_TRSV, tri_bytes, [&] {
-    return launch_trsv<R>(true, Lt, Li, b.n_pad, b.g, b.y, nullptr, c->area(1), c->fwd_flags(),
-                          &lm->timeout, lm, 1, st);
-  }));
   DDCCK(timed(c, T_TRSV, tri_bytes, [&] {
     return launch_trsv<R>(false, Lt, Li, b.n_pad, b.y, b.d, nullptr, c->area(2), c->bwd_flags(),
                           &lm->timeout, lm, 1, st);
@@ -400,7 +397,7 @@ ddc_status ddc_create(ddc_ctx** out, int32_t device) {
     return DDC_EDEVICE;
   }
   hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->chol_wg = 2 * prop.multiProcessorCount;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->chol_wg = prop.multiProcessorCount;
   *out = c;
   return DDC_OK;
 }

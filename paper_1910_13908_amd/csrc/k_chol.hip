@@ -5,12 +5,15 @@
 // lower triangle from an atomic ticket in column-major tile order, and each tile is owned by
 // one workgroup from its first update to its final value (left-looking):
 //
-//   A_IJ <- H_IJ + mu [I==J] - sum_{K<J} L_IK L_JK^T      (MFMA, operands staged in LDS)
-//   I == J:  L_JJ = chol(A_JJ), and its inverse;          (one wave, registers + LDS)
-//   I >  J:  L_IJ = A_IJ L_JJ^{-T}                        (MFMA with the stored inverse)
+//   A_IJ <- H_IJ + mu [I==J] - sum_{K<J} L_IK L_JK^T      (MFMA, double-buffered LDS operands)
+//   I == J:  L_JJ = chol(A_JJ) and X_JJ = L_JJ^{-1}       (blocked 16-column panels + MFMA)
+//   I >  J:  L_IJ = A_IJ X_JJ^T                           (MFMA with the stored inverse)
 //
-// A tile publishes a ready flag when it is final; a consumer waits only on flags of tiles
-// with a smaller ticket.  Tickets are claimed only by running workgroups, so the smallest
+// The task that factors diagonal tile s first computes the subdiagonal tile (s, s-1)
+// itself, so the chain of dependent diagonal factorisations has one inter-workgroup hand-off
+// per 64 columns.  With a right-hand side g the same kernel also runs the forward
+// substitution y = L^{-1} g block by block as the factor appears.  A tile publishes a ready
+// flag when it is final; a consumer waits only on flags of tasks with a smaller ticket.  Tickets are claimed only by running workgroups, so the smallest
 // unfinished ticket never waits on unfinished work and the schedule cannot deadlock without
 // any co-residency guarantee.  Every wait is bounded; on expiry the kernel raises an abort
 // flag, every other wait returns at once, and the status word reports DDC_ETIMEOUT.  The
@@ -33,6 +36,7 @@ constexpr uint32_t kSpinLimit = 1u << 22;   // polls (with s_sleep) before a wai
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 template <typename R>
 struct Mfma;
@@ -116,7 +120,8 @@ __device__ __forceinline__ void publish(uint32_t* flag) {
 }
 
 // Leave the persistent loop; the last workgroup out clears the flags and the counters.
-__device__ void exit_and_reset(SyncArea* sync, uint32_t* flags, int nflags) {
+__device__ void exit_and_reset(SyncArea* sync, uint32_t* flags, int nflags,
+                               uint32_t* flags2 = nullptr, int nflags2 = 0) {
   __shared__ int s_last;
   __threadfence();
   __syncthreads();
@@ -125,6 +130,7 @@ __device__ void exit_and_reset(SyncArea* sync, uint32_t* flags, int nflags) {
   if (s_last) {
     __threadfence();
     for (int i = threadIdx.x; i < nflags; i += blockDim.x) flags[i] = 0u;
+    for (int i = threadIdx.x; i < nflags2; i += blockDim.x) flags2[i] = 0u;
     if (threadIdx.x == 0) {
       sync->ticket = 0u;
       sync->exited = 0u;
@@ -148,20 +154,20 @@ template <typename R>
 __device__ __forceinline__ void tile_to_lds(const R* __restrict__ src, R* dst) {
   constexpr int STR = Mfma<R>::STR;
   if constexpr (sizeof(R) == 4) {
-    const float4* s4 = reinterpret_cast<const float4*>(src);
+    const f32x4* s4 = reinterpret_cast<const f32x4*>(src);
 #pragma unroll
     for (int it = 0; it < 4; ++it) {
-      const int idx = threadIdx.x + it * kThreads;       // 1024 float4
+      const int idx = threadIdx.x + it * kThreads;       // 1024 x 4 floats
       const int r = idx >> 4, c = (idx & 15) * 4;
-      *reinterpret_cast<float4*>(dst + r * STR + c) = s4[idx];
+      *reinterpret_cast<f32x4*>(dst + r * STR + c) = s4[idx];
     }
   } else {
-    const double2* s2 = reinterpret_cast<const double2*>(src);
+    const f64x2* s2 = reinterpret_cast<const f64x2*>(src);
 #pragma unroll
     for (int it = 0; it < 8; ++it) {
-      const int idx = threadIdx.x + it * kThreads;       // 2048 double2
+      const int idx = threadIdx.x + it * kThreads;       // 2048 x 2 doubles
       const int r = idx >> 5, c = (idx & 31) * 2;
-      *reinterpret_cast<double2*>(dst + r * STR + c) = s2[idx];
+      *reinterpret_cast<f64x2*>(dst + r * STR + c) = s2[idx];
     }
   }
 }
@@ -179,15 +185,26 @@ __device__ __forceinline__ void tile_mma(typename Mfma<R>::acc_t (&acc)[2][2], c
   const R* a1 = a0 + 16 * STR;
   const R* b0 = B + (qc * 32 + rr) * STR + 16 * g;
   const R* b1 = b0 + 16 * STR;
+  // four chunks of four consecutive k per lane keep only 16 operand values live
 #pragma unroll
-  for (int s = 0; s < 16; ++s) {
-    const R x0 = NEG ? -a0[s] : a0[s];
-    const R x1 = NEG ? -a1[s] : a1[s];
-    const R y0 = b0[s], y1 = b1[s];
-    acc[0][0] = Mfma<R>::mma(x0, y0, acc[0][0]);
-    acc[0][1] = Mfma<R>::mma(x0, y1, acc[0][1]);
-    acc[1][0] = Mfma<R>::mma(x1, y0, acc[1][0]);
-    acc[1][1] = Mfma<R>::mma(x1, y1, acc[1][1]);
+  for (int ch = 0; ch < 4; ++ch) {
+    R x0[4], x1[4], y0[4], y1[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      x0[u] = a0[4 * ch + u];
+      x1[u] = a1[4 * ch + u];
+      y0[u] = b0[4 * ch + u];
+      y1[u] = b1[4 * ch + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const R p0 = NEG ? -x0[u] : x0[u];
+      const R p1 = NEG ? -x1[u] : x1[u];
+      acc[0][0] = Mfma<R>::mma(p0, y0[u], acc[0][0]);
+      acc[0][1] = Mfma<R>::mma(p0, y1[u], acc[0][1]);
+      acc[1][0] = Mfma<R>::mma(p1, y0[u], acc[1][0]);
+      acc[1][1] = Mfma<R>::mma(p1, y1[u], acc[1][1]);
+    }
   }
 }
 
@@ -224,143 +241,435 @@ __device__ __forceinline__ void acc_to_global(const typename Mfma<R>::acc_t (&ac
       }
 }
 
-// Cholesky of the lower triangle of a 64x64 LDS tile in place (wave 0; lane i owns row i).
-// Crout order: column j needs row j of L (k < j) from LDS and the lane's own row from
-// registers.  Returns nonzero in lane 0 if a pivot was not positive (it is then set to 1 so
-// that the factorisation still finishes with finite values).
+// ---------------------------------------------------------------------------------------
+// Diagonal tile: Cholesky factor and inverse of a 64x64 LDS tile (row-major, stride STR).
+// Blocked right-looking with 16-column panels: wave 0 factors a panel (lane i owns row i,
+// Crout order inside the panel, pivots broadcast with readlane, 1/sqrt via rsq), then all
+// four waves apply the rank-16 trailing update with MFMA.  The inverse X = L^{-1} is built
+// from the four 16x16 diagonal inverses (one wave each, forward substitution) and, block
+// row by block row, X_ij = -X_ii sum_{k=j}^{i-1} L_ik X_kj with MFMA.
+// ---------------------------------------------------------------------------------------
+
+// Index inside a 16-wide reduction walked by lane group g at step s, chosen so that an
+// MFMA result element v = s of lane l is exactly the B operand that lane needs.
 template <typename R>
-__device__ int potrf_wave(R* A) {
+__device__ __forceinline__ int kwalk16(int g, int s) {
+  return sizeof(R) == 4 ? 4 * g + s : g + 4 * s;
+}
+
+__device__ __forceinline__ float bcast_lane(float x, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
+}
+__device__ __forceinline__ double bcast_lane(double x, int lane) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ float rsq_full(float d) { return __builtin_amdgcn_rsqf(d); }
+__device__ __forceinline__ double rsq_full(double d) {
+  double r = __builtin_amdgcn_rsq(d);
+  // two Newton steps r <- r (3 - d r^2) / 2 take the hardware estimate to full precision
+  r = r * fma(-0.5 * d, r * r, 1.5);
+  r = r * fma(-0.5 * d, r * r, 1.5);
+  return r;
+}
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Wave 0: factor columns 16P..16P+15 (rows >= 16P) in place; returns nonzero on a bad pivot.
+template <typename R, int P>
+__device__ int panel_factor(R* A, R* rdiag) {
   constexpr int STR = Mfma<R>::STR;
+  constexpr int c0 = 16 * P;
   const int i = threadIdx.x & 63;
-  R a[64];
+  R a[16];
 #pragma unroll
-  for (int k = 0; k < 64; ++k) a[k] = A[i * STR + k];
+  for (int j = 0; j < 16; ++j) a[j] = A[i * STR + c0 + j];
   int bad = 0;
 #pragma unroll
-  for (int j = 0; j < 64; ++j) {
-    R dot = 0;
-    const R* rowj = A + j * STR;
+  for (int j = 0; j < 16; ++j) {
+    const int c = c0 + j;
+    const R* rowc = A + c * STR + c0;
+    R d0 = 0, d1 = 0;
 #pragma unroll
-    for (int k = 0; k < j; ++k) dot = fma(a[k], rowj[k], dot);
-    const R x = a[j] - dot;
-    R d = __shfl(x, j, 64);
+    for (int k = 0; k < j; k += 2) {
+      d0 = fma(a[k], rowc[k], d0);
+      if (k + 1 < j) d1 = fma(a[k + 1], rowc[k + 1], d1);
+    }
+    const R x = a[j] - (d0 + d1);
+    R d = bcast_lane(x, c);
     if (!(d > (R)0) || !(d < (R)INFINITY)) {
       bad = 1;
       d = (R)1;
     }
-    const R ljj = sqrt(d);
-    const R lij = (i == j) ? ljj : x / ljj;
-    a[j] = lij;
-    if (i >= j) A[i * STR + j] = lij;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const R r = rsq_full(d);
+    const R lic = (i == c) ? d * r : x * r;
+    a[j] = lic;
+    if (i >= c) A[i * STR + c] = lic;
+    if (i == c) rdiag[c] = r;
+    wave_sync_lds();
   }
   return bad;
 }
 
-// X = L^{-1} for the lower-triangular 64x64 L in LDS tile A (wave 0; lane c owns column c
-// of X).  Row-oriented substitution: X[i][c] = ([i==c] - sum_{k<i} L[i][k] X[k][c]) / L[i][i].
-template <typename R>
-__device__ void trinv_wave(const R* A, R* X) {
+// All waves: A[r][c] -= sum_{k in panel P} A[r][k] A[c][k] for the lower 16x16 blocks right
+// of and below panel P.
+template <typename R, int P>
+__device__ void panel_update(R* A) {
   constexpr int STR = Mfma<R>::STR;
-  const int c = threadIdx.x & 63;
-  R x[64];
+  constexpr int c0 = 16 * P;
+  constexpr int nb = 3 - P;
+  constexpr int nblk = nb * (nb + 1) / 2;
+  using acc_t = typename Mfma<R>::acc_t;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, rr = lane & 15;
+  for (int blk = wv; blk < nblk; blk += 4) {
+    int br = P + 1, bc = P + 1, t = blk;
+    while (t > br - (P + 1)) {
+      t -= br - P;
+      ++br;
+    }
+    bc = P + 1 + t;
+    acc_t acc;
 #pragma unroll
-  for (int i = 0; i < 64; ++i) {
-    const R* rowi = A + i * STR;
-    R dot = 0;
+    for (int v = 0; v < 4; ++v)
+      acc[v] = A[(16 * br + out_row<R>(lane, v)) * STR + 16 * bc + out_col(lane, v)];
 #pragma unroll
-    for (int k = 0; k < i; ++k) dot = fma(rowi[k], x[k], dot);
-    x[i] = ((i == c ? (R)1 : (R)0) - dot) / rowi[i];
+    for (int s = 0; s < 4; ++s) {
+      const int k = c0 + 4 * g + s;
+      acc = Mfma<R>::mma(-A[(16 * br + rr) * STR + k], A[(16 * bc + rr) * STR + k], acc);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      A[(16 * br + out_row<R>(lane, v)) * STR + 16 * bc + out_col(lane, v)] = acc[v];
   }
+}
+
+// Factor the tile in A (lower triangle) in place and write X = L^{-1} into X.  Returns
+// nonzero (in every thread) if a pivot was not positive.
+template <typename R>
+__device__ int cholinv_tile(R* A, R* X, R* rdiag) {
+  constexpr int STR = Mfma<R>::STR;
+  using acc_t = typename Mfma<R>::acc_t;
+  __shared__ int s_bad;
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63, g = lane >> 4, rr = lane & 15;
+  int bad = 0;
+  if (wv == 0) bad |= panel_factor<R, 0>(A, rdiag);
+  __syncthreads();
+  panel_update<R, 0>(A);
+  __syncthreads();
+  if (wv == 0) bad |= panel_factor<R, 1>(A, rdiag);
+  __syncthreads();
+  panel_update<R, 1>(A);
+  __syncthreads();
+  if (wv == 0) bad |= panel_factor<R, 2>(A, rdiag);
+  __syncthreads();
+  panel_update<R, 2>(A);
+  __syncthreads();
+  if (wv == 0) {
+    bad |= panel_factor<R, 3>(A, rdiag);
+    if (lane == 0) s_bad = bad;
+  }
+  // inverse of the diagonal 16x16 blocks: wave w takes block w, lane c < 16 column c
+  for (int e = tid; e < 64 * 64; e += kThreads) {
+    const int r = e >> 6, c = e & 63;
+    if ((c >> 4) > (r >> 4)) X[r * STR + c] = (R)0;
+  }
+  __syncthreads();
+  if (lane < 16) {
+    const int b0 = 16 * wv, c = lane;
+    R x[16];
 #pragma unroll
-  for (int i = 0; i < 64; ++i) X[i * STR + c] = x[i];
+    for (int i = 0; i < 16; ++i) {
+      const R* rowi = A + (b0 + i) * STR + b0;
+      R d0 = 0, d1 = 0;
+#pragma unroll
+      for (int k = 0; k < i; k += 2) {
+        d0 = fma(rowi[k], x[k], d0);
+        if (k + 1 < i) d1 = fma(rowi[k + 1], x[k + 1], d1);
+      }
+      x[i] = ((i == c ? (R)1 : (R)0) - (d0 + d1)) * rdiag[b0 + i];
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) X[(b0 + i) * STR + b0 + c] = x[i];
+  }
+  __syncthreads();
+  // off-diagonal blocks, one block row at a time: X_ij = -X_ii sum_{k=j}^{i-1} L_ik X_kj
+  for (int i = 1; i < 4; ++i) {
+    const int j = wv;
+    if (j < i) {
+      acc_t t = acc_t{0, 0, 0, 0};
+      for (int k = j; k < i; ++k) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int m = kwalk16<R>(g, s);
+          t = Mfma<R>::mma(A[(16 * i + rr) * STR + 16 * k + m], X[(16 * k + m) * STR + 16 * j + rr], t);
+        }
+      }
+      acc_t o = acc_t{0, 0, 0, 0};
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        o = Mfma<R>::mma(-X[(16 * i + rr) * STR + 16 * i + kwalk16<R>(g, s)], t[s], o);
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        X[(16 * i + out_row<R>(lane, v)) * STR + 16 * j + out_col(lane, v)] = o[v];
+    }
+    __syncthreads();
+  }
+  return s_bad;
+}
+
+// ---------------------------------------------------------------------------------------
+// Operand staging for the tile updates: one 64x64 packed tile is 16 elements per thread.
+// ---------------------------------------------------------------------------------------
+template <typename R>
+struct TileRegs;
+template <>
+struct TileRegs<float> {
+  f32x4 v[4];
+};
+template <>
+struct TileRegs<double> {
+  f64x2 v[8];
+};
+
+template <typename R>
+__device__ __forceinline__ void tile_fetch(const R* __restrict__ src, TileRegs<R>& t) {
+  if constexpr (sizeof(R) == 4) {
+    const f32x4* s4 = reinterpret_cast<const f32x4*>(src);
+#pragma unroll
+    for (int it = 0; it < 4; ++it) t.v[it] = s4[threadIdx.x + it * kThreads];
+  } else {
+    const f64x2* s2 = reinterpret_cast<const f64x2*>(src);
+#pragma unroll
+    for (int it = 0; it < 8; ++it) t.v[it] = s2[threadIdx.x + it * kThreads];
+  }
 }
 
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_cholesky(
-    const R* __restrict__ Hc, int64_t ld, int T, const double* __restrict__ mu_dev, double mu_host,
-    R* __restrict__ Lt, R* __restrict__ Linv, SyncArea* sync, uint32_t* flags,
-    int32_t* status) {
+__device__ __forceinline__ void tile_stash(const TileRegs<R>& t, R* dst) {
   constexpr int STR = Mfma<R>::STR;
+  if constexpr (sizeof(R) == 4) {
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int idx = threadIdx.x + it * kThreads;
+      *reinterpret_cast<f32x4*>(dst + (idx >> 4) * STR + (idx & 15) * 4) = t.v[it];
+    }
+  } else {
+#pragma unroll
+    for (int it = 0; it < 8; ++it) {
+      const int idx = threadIdx.x + it * kThreads;
+      *reinterpret_cast<f64x2*>(dst + (idx >> 5) * STR + (idx & 31) * 2) = t.v[it];
+    }
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void acc_load_h(typename Mfma<R>::acc_t (&acc)[2][2],
+                                           const R* __restrict__ Hc, int64_t ld, int I, int J,
+                                           double mu, int qr, int qc) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = qr * 32 + bi * 16 + out_row<R>(lane, v);
+        const int c = qc * 32 + bj * 16 + out_col(lane, v);
+        R h = Hc[(int64_t)(64 * J + c) * ld + 64 * I + r];
+        if (I == J && r == c) h = (R)((double)h + mu);
+        acc[bi][bj][v] = h;
+      }
+}
+
+// Task kinds of the factorisation, in ticket order per step s:
+//   D_s: tile (s, s-1) (s >= 1) and the diagonal tile (s, s) with its inverse;
+//   Y_s: forward-substitution block y_s = X_ss (g_s - sum_{K<s} L_sK y_K);
+//   R_{s-1}: tiles (I, s-1), I >= s+1 (regular tiles of column s-1).
+// Every task depends only on tasks earlier in this order.
+enum { TASK_D = 0, TASK_Y = 1, TASK_R = 2, TASK_NONE = 3 };
+
+__device__ __forceinline__ void decode_task(uint32_t t, int T, int& kind, int& I, int& J) {
+  kind = TASK_NONE;
+  I = J = 0;
+  if (t == 0) { kind = TASK_D; return; }
+  if (t == 1) { kind = TASK_Y; return; }
+  t -= 2;
+  for (int s = 1; s < T; ++s) {
+    const uint32_t nr = (uint32_t)max(0, T - s - 1);
+    if (t < 2 + nr) {
+      if (t == 0) { kind = TASK_D; I = J = s; }
+      else if (t == 1) { kind = TASK_Y; I = J = s; }
+      else { kind = TASK_R; J = s - 1; I = s + 1 + (int)(t - 2); }
+      return;
+    }
+    t -= 2 + nr;
+  }
+}
+
+__host__ __device__ inline uint32_t chol_tasks(int T) {
+  return (uint32_t)(2 * T + (T >= 2 ? (T - 2) * (T - 1) / 2 : 0));
+}
+
+// Accumulate acc1 -= A_K B_K^T (and acc2 -= A_K A_K^T when TWO) over K < nK, where
+// A_K = L(IA, K), B_K = L(IB, K), with a double-buffered LDS pipeline: the next pair of
+// tiles is fetched into registers while the current pair feeds the MFMAs.
+template <typename R, bool TWO>
+__device__ __forceinline__ bool accumulate(typename Mfma<R>::acc_t (&acc1)[2][2],
+                                           typename Mfma<R>::acc_t (&acc2)[2][2],
+                           const R* __restrict__ Lt, int T, int IA, int IB, int nK, R* lds,
+                           SyncArea* sync, uint32_t* flags, int32_t* status, int qr, int qc) {
+  constexpr int STR = Mfma<R>::STR;
+  constexpr int TILE = 64 * STR;
+  if (nK <= 0) return true;
+  TileRegs<R> ra, rb;
+  bool ok = wait_flag(flags + tile_index(IA, 0, T), sync, status);
+  if (ok && IB != IA) ok = wait_flag(flags + tile_index(IB, 0, T), sync, status);
+  tile_fetch<R>(Lt + (int64_t)tile_index(IA, 0, T) * 4096, ra);
+  tile_fetch<R>(Lt + (int64_t)tile_index(IB, 0, T) * 4096, rb);
+  tile_stash<R>(ra, lds);
+  tile_stash<R>(rb, lds + TILE);
+  __syncthreads();
+  int buf = 0;
+  for (int K = 0; K < nK; ++K) {
+    const bool more = K + 1 < nK;
+    if (more && ok) {
+      ok = wait_flag(flags + tile_index(IA, K + 1, T), sync, status);
+      if (ok && IB != IA) ok = wait_flag(flags + tile_index(IB, K + 1, T), sync, status);
+      tile_fetch<R>(Lt + (int64_t)tile_index(IA, K + 1, T) * 4096, ra);
+      tile_fetch<R>(Lt + (int64_t)tile_index(IB, K + 1, T) * 4096, rb);
+    }
+    const R* As = lds + buf * 2 * TILE;
+    tile_mma<R, true>(acc1, As, As + TILE, qr, qc);
+    if constexpr (TWO) tile_mma<R, true>(acc2, As, As, qr, qc);
+    if (more) {
+      R* nxt = lds + (buf ^ 1) * 2 * TILE;
+      tile_stash<R>(ra, nxt);
+      tile_stash<R>(rb, nxt + TILE);
+    }
+    __syncthreads();
+    buf ^= 1;
+  }
+  return ok;
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_cholesky(
+    const R* __restrict__ Hc, int64_t ld, int T, const double* __restrict__ mu_dev, double mu_host,
+    const double* __restrict__ gvec, double* __restrict__ yvec, R* __restrict__ Lt,
+    R* __restrict__ Linv, SyncArea* sync, uint32_t* flags, uint32_t* yflags, int32_t* status) {
+  constexpr int STR = Mfma<R>::STR;
+  constexpr int TILE = 64 * STR;
   using acc_t = typename Mfma<R>::acc_t;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  R* As = reinterpret_cast<R*>(smem_raw);
-  R* Bs = As + 64 * STR;
+  R* lds = reinterpret_cast<R*>(smem_raw);            // 4 tiles: two double-buffered pairs
+  __shared__ R rdiag[64];
+  __shared__ double s_vec[64];
+  __shared__ double s_red[kThreads];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int qr = wv >> 1, qc = wv & 1;
   const double mu = mu_dev ? *mu_dev : mu_host;
-  const uint32_t ntasks = (uint32_t)(T * (T + 1) / 2);
+  const uint32_t ntasks = chol_tasks(T);
 
   for (;;) {
     const uint32_t t = claim(sync);
     if (t >= ntasks) break;
-    int I, J;
-    decode_ticket(t, T, I, J);
-
-    acc_t acc[2][2];
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int r = qr * 32 + bi * 16 + out_row<R>(lane, v);
-          const int c = qc * 32 + bj * 16 + out_col(lane, v);
-          R h = Hc[(int64_t)(64 * J + c) * ld + 64 * I + r];
-          if (I == J && r == c) h = (R)((double)h + mu);
-          acc[bi][bj][v] = h;
-        }
-
+    int kind, I, J;
+    decode_task(t, T, kind, I, J);
     bool ok = true;
-    for (int K = 0; K < J && ok; ++K) {
-      ok = wait_flag(flags + tile_index(I, K, T), sync, status);
-      if (ok && I != J) ok = wait_flag(flags + tile_index(J, K, T), sync, status);
-      if (!ok) break;
-      tile_to_lds<R>(Lt + (int64_t)tile_index(I, K, T) * 4096, As);
-      if (I != J) tile_to_lds<R>(Lt + (int64_t)tile_index(J, K, T) * 4096, Bs);
-      __syncthreads();
-      tile_mma<R, true>(acc, As, I != J ? Bs : As, qr, qc);
-      __syncthreads();
-    }
 
-    if (I == J) {
-      acc_to_lds<R>(acc, As, qr, qc);
-      __syncthreads();
-      __shared__ int s_bad;
-      if (wv == 0) {
-        const int bad = potrf_wave<R>(As);
-        if (lane == 0) s_bad = bad;
-      }
-      __syncthreads();
-      if (s_bad && tid == 0 && status) atomicOr(status, 1);
-      if (wv == 0) trinv_wave<R>(As, Bs);
-      __syncthreads();
-      R* dstL = Lt + (int64_t)tile_index(J, J, T) * 4096;
-      R* dstI = Linv + (int64_t)J * 4096;
-      for (int e = tid; e < 4096; e += kThreads) {
-        const int r = e >> 6, c = e & 63;
-        dstL[e] = (c <= r) ? As[r * STR + c] : (R)0;
-        dstI[e] = (c <= r) ? Bs[r * STR + c] : (R)0;
-      }
-    } else {
+    if (kind == TASK_R) {
+      acc_t acc[2][2], dummy[2][2];
+      acc_load_h<R>(acc, Hc, ld, I, J, 0.0, qr, qc);
+      ok = accumulate<R, false>(acc, dummy, Lt, T, I, J, J, lds, sync, flags, status, qr, qc);
       if (ok) ok = wait_flag(flags + tile_index(J, J, T), sync, status);
-      acc_to_lds<R>(acc, As, qr, qc);
-      if (ok) tile_to_lds<R>(Linv + (int64_t)J * 4096, Bs);
+      acc_to_lds<R>(acc, lds, qr, qc);
+      tile_to_lds<R>(Linv + (int64_t)J * 4096, lds + TILE);
       __syncthreads();
       acc_t out[2][2];
 #pragma unroll
       for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj) out[bi][bj] = acc_t{0, 0, 0, 0};
-      tile_mma<R, false>(out, As, Bs, qr, qc);
+      tile_mma<R, false>(out, lds, lds + TILE, qr, qc);
       acc_to_global<R>(out, Lt + (int64_t)tile_index(I, J, T) * 4096, qr, qc);
+      publish(flags + tile_index(I, J, T));
+      __syncthreads();
+    } else if (kind == TASK_D) {
+      const int s = J;
+      acc_t accd[2][2];
+      acc_load_h<R>(accd, Hc, ld, s, s, mu, qr, qc);
+      if (s >= 1) {
+        acc_t accs[2][2];
+        acc_load_h<R>(accs, Hc, ld, s, s - 1, 0.0, qr, qc);
+        ok = accumulate<R, true>(accs, accd, Lt, T, s, s - 1, s - 1, lds, sync, flags, status, qr, qc);
+        if (ok) ok = wait_flag(flags + tile_index(s - 1, s - 1, T), sync, status);
+        acc_to_lds<R>(accs, lds, qr, qc);
+        tile_to_lds<R>(Linv + (int64_t)(s - 1) * 4096, lds + TILE);
+        __syncthreads();
+        acc_t ls[2][2];
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj) ls[bi][bj] = acc_t{0, 0, 0, 0};
+        tile_mma<R, false>(ls, lds, lds + TILE, qr, qc);
+        acc_to_global<R>(ls, Lt + (int64_t)tile_index(s, s - 1, T) * 4096, qr, qc);
+        __syncthreads();
+        acc_to_lds<R>(ls, lds + 2 * TILE, qr, qc);
+        publish(flags + tile_index(s, s - 1, T));
+        __syncthreads();
+        tile_mma<R, true>(accd, lds + 2 * TILE, lds + 2 * TILE, qr, qc);
+        __syncthreads();
+      }
+      acc_to_lds<R>(accd, lds, qr, qc);
+      __syncthreads();
+      const int bad = cholinv_tile<R>(lds, lds + TILE, rdiag);
+      if (bad && tid == 0 && status) atomicOr(status, 1);
+      R* dstL = Lt + (int64_t)tile_index(s, s, T) * 4096;
+      R* dstX = Linv + (int64_t)s * 4096;
+      for (int e = tid; e < 4096; e += kThreads) {
+        const int r = e >> 6, c = e & 63;
+        dstL[e] = (c <= r) ? lds[r * STR + c] : (R)0;
+        dstX[e] = lds[TILE + r * STR + c];
+      }
+      publish(flags + tile_index(s, s, T));
+      __syncthreads();
+    } else if (kind == TASK_Y && gvec) {
+      // y_J = X_JJ (g_J - sum_{K<J} L_JK y_K), FP64 accumulation
+      const int r = tid & 63, part = tid >> 6;
+      double acc = 0.0;
+      for (int K = 0; K < J && ok; ++K) {
+        ok = wait_flag(flags + tile_index(J, K, T), sync, status);
+        if (ok) ok = wait_flag(yflags + K, sync, status);
+        const R* tile = Lt + (int64_t)tile_index(J, K, T) * 4096 + r * 64 + part * 16;
+        const double* yv = yvec + 64 * K + part * 16;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) acc = fma((double)tile[c], yv[c], acc);
+      }
+      s_red[tid] = acc;
+      __syncthreads();
+      if (tid < 64)
+        s_vec[tid] = gvec[64 * J + tid] - (((s_red[tid] + s_red[tid + 64]) + s_red[tid + 128]) + s_red[tid + 192]);
+      if (ok) ok = wait_flag(flags + tile_index(J, J, T), sync, status);
+      const R* inv = Linv + (int64_t)J * 4096 + r * 64 + part * 16;
+      double y = 0.0;
+#pragma unroll
+      for (int c = 0; c < 16; ++c) y = fma((double)inv[c], s_vec[part * 16 + c], y);
+      s_red[tid] = y;
+      __syncthreads();
+      if (tid < 64)
+        yvec[64 * J + tid] = ((s_red[tid] + s_red[tid + 64]) + s_red[tid + 128]) + s_red[tid + 192];
+      publish(yflags + J);
+      __syncthreads();
     }
-    publish(flags + tile_index(I, J, T));
-    __syncthreads();
   }
-  exit_and_reset(sync, flags, (int)ntasks);
+  exit_and_reset(sync, flags, (int)(T * (T + 1) / 2), yflags, yflags ? T : 0);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -530,18 +839,19 @@ __global__ __launch_bounds__(kThreads) void k_refine_resid(
 
 template <typename R>
 size_t chol_smem_bytes() {
-  return 2 * 64 * Mfma<R>::STR * sizeof(R);
+  return 4 * 64 * Mfma<R>::STR * sizeof(R);
 }
 
 template <typename R>
 hipError_t launch_cholesky(const R* Hc, int ld, int n_pad, const double* mu_dev, double mu_host,
-                           R* Lt, R* Linv, SyncArea* sync, uint32_t* flags, int32_t* status,
-                           const LMState*, hipStream_t st, int n_wg) {
+                           const double* g, double* y, R* Lt, R* Linv, SyncArea* sync,
+                           uint32_t* flags, uint32_t* yflags, int32_t* status, hipStream_t st,
+                           int n_wg) {
   const int T = n_pad / 64;
-  const int ntasks = T * (T + 1) / 2;
+  const int ntasks = (int)chol_tasks(T);
   const int grid = n_wg < ntasks ? n_wg : ntasks;
   hipLaunchKernelGGL(k_cholesky<R>, dim3(grid), dim3(kThreads), chol_smem_bytes<R>(), st, Hc,
-                     (int64_t)ld, T, mu_dev, mu_host, Lt, Linv, sync, flags, status);
+                     (int64_t)ld, T, mu_dev, mu_host, g, y, Lt, Linv, sync, flags, yflags, status);
   return hipGetLastError();
 }
 
@@ -580,9 +890,9 @@ hipError_t set_chol_smem_attr() {
 }
 
 #define DDC_INST(R)                                                                           \
-  template hipError_t launch_cholesky<R>(const R*, int, int, const double*, double, R*, R*,    \
-                                         SyncArea*, uint32_t*, int32_t*, const LMState*,       \
-                                         hipStream_t, int);                                    \
+  template hipError_t launch_cholesky<R>(const R*, int, int, const double*, double,             \
+                                         const double*, double*, R*, R*, SyncArea*, uint32_t*, \
+                                         uint32_t*, int32_t*, hipStream_t, int);               \
   template hipError_t launch_trsv<R>(bool, const R*, const R*, int, const double*, double*,    \
                                      double*, SyncArea*, uint32_t*, int32_t*, const LMState*,  \
                                      int, hipStream_t);                                        \

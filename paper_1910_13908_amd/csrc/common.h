@@ -97,10 +97,12 @@ template <typename R>
 hipError_t launch_trsv(bool forward, const R* Lt, const R* Linv, int n_pad, const double* b,
                        double* x, double* acc_out, SyncArea* sync, uint32_t* flags,
                        int32_t* status, const LMState* lm, int gate, hipStream_t st);
+// s = g - (H + mu I) d (FP64) via per-tile partials prow/pcol ([T(T+1)/2][64] each).
 template <typename R>
 hipError_t launch_refine_resid(const R* Hc, int ld, int n_pad, const double* mu_dev,
                                const double* g, const double* d, double* s, double* s_part,
-                               const LMState* lm, int gate, hipStream_t st);
+                               double* prow, double* pcol, const LMState* lm, int gate,
+                               hipStream_t st);
 hipError_t set_chol_smem_attr();
 
 // k_lm.hip

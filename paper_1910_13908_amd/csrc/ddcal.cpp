@@ -216,7 +216,7 @@ ddc_status obs_dev(ddc_ctx* c, const ddc_obs* o, ObsDev& d) {
 struct SolveBufs {
   int n, n_pad, T, ld;
   void *Hc, *Lt, *Linv, *part;
-  double *g, *diag, *d, *y, *s, *e, *cost_part, *s_part, *scalar;
+  double *g, *diag, *d, *y, *s, *e, *cost_part, *s_part, *scalar, *prow, *pcol;
   size_t h_off;
 };
 
@@ -236,6 +236,9 @@ void layout_solve(Bump& bp, SolveBufs& b, int n, size_t es, int64_t B, int64_t n
   offs.push_back(bp.take((size_t)(nblk_max > 0 ? nblk_max : 1) * sizeof(double)));  // cost_part
   offs.push_back(bp.take((size_t)b.T * sizeof(double)));                // s_part
   offs.push_back(bp.take(64 * sizeof(double)));                         // scalars
+  const size_t ntiles = (size_t)b.T * (b.T + 1) / 2;
+  offs.push_back(bp.take(ntiles * 64 * sizeof(double)));               // prow
+  offs.push_back(bp.take(ntiles * 64 * sizeof(double)));               // pcol
 }
 
 void bind_solve(ddc_ctx* c, SolveBufs& b, const std::vector<size_t>& o) {
@@ -253,6 +256,8 @@ void bind_solve(ddc_ctx* c, SolveBufs& b, const std::vector<size_t>& o) {
   b.cost_part = reinterpret_cast<double*>(w + o[10]);
   b.s_part = reinterpret_cast<double*>(w + o[11]);
   b.scalar = reinterpret_cast<double*>(w + o[12]);
+  b.prow = reinterpret_cast<double*>(w + o[13]);
+  b.pcol = reinterpret_cast<double*>(w + o[14]);
   b.h_off = o[0];
 }
 
@@ -291,8 +296,8 @@ ddc_status enqueue_solve(ddc_ctx* c, SolveBufs& b, LMState* lm, int refine_max, 
   }));
   for (int r = 0; r < refine_max; ++r) {
     DDCCK(timed(c, T_REFINE, (double)b.n_pad * b.n_pad * sizeof(R), [&] {
-      return launch_refine_resid<R>(Hc, b.ld, b.n_pad, &lm->mu_eff, b.g, b.d, b.s, b.s_part, lm,
-                                    2, st);
+      return launch_refine_resid<R>(Hc, b.ld, b.n_pad, &lm->mu_eff, b.g, b.d, b.s, b.s_part,
+                                    b.prow, b.pcol, lm, 2, st);
     }));
     HIPCK(launch_refine_ctrl(lm, b.s_part, b.T, tol * tol, st));
     DDCCK(timed(c, T_TRSV, tri_bytes, [&] {

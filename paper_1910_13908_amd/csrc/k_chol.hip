@@ -696,7 +696,9 @@ __device__ __forceinline__ double reduce4(double v, double* sh) {
   return r;
 }
 
-// Forward: x = L^{-1} b.  Task I (in ticket order): s = b_I - sum_{K<I} L_IK x_K; x_I = Linv_II s.
+// Forward: x = L^{-1} b.  Task I (in ticket order): s = b_I - sum_{K<I} L_IK x_K; x_I = X_II s.
+// The factor is complete before this kernel starts, so tile operands are fetched ahead of
+// the wait on each solution block; only x_K itself is waited for.
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_trsv_fwd(
     const R* __restrict__ Lt, const R* __restrict__ Linv, int T, const double* __restrict__ b,
@@ -713,23 +715,36 @@ __global__ __launch_bounds__(kThreads) void k_trsv_fwd(
     const uint32_t t = claim(sync);
     if (t >= (uint32_t)T) break;
     const int I = (int)t;
+    R xinv[16], cur[16], nxt[16];
+    const R* inv = Linv + (int64_t)I * 4096 + r * 64 + part * 16;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) xinv[c] = inv[c];
+    if (I > 0) {
+      const R* tile = Lt + (int64_t)tile_index(I, 0, T) * 4096 + r * 64 + part * 16;
+#pragma unroll
+      for (int c = 0; c < 16; ++c) nxt[c] = tile[c];
+    }
     double acc = 0.0;
     bool ok = true;
     for (int K = 0; K < I; ++K) {
-      ok = wait_flag(flags + K, sync, status);
-      if (!ok) break;
-      const R* tile = Lt + (int64_t)tile_index(I, K, T) * 4096 + r * 64 + part * 16;
+#pragma unroll
+      for (int c = 0; c < 16; ++c) cur[c] = nxt[c];
+      if (K + 1 < I) {
+        const R* tile = Lt + (int64_t)tile_index(I, K + 1, T) * 4096 + r * 64 + part * 16;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) nxt[c] = tile[c];
+      }
+      if (ok) ok = wait_flag(flags + K, sync, status);
       const double* xv = x + 64 * K + part * 16;
 #pragma unroll
-      for (int c = 0; c < 16; ++c) acc = fma((double)tile[c], xv[c], acc);
+      for (int c = 0; c < 16; ++c) acc = fma((double)cur[c], xv[c], acc);
     }
     const double sum = reduce4(acc, sh);
     if (tid < 64) s_vec[tid] = b[64 * I + tid] - sum;
     __syncthreads();
-    const R* inv = Linv + (int64_t)I * 4096 + r * 64 + part * 16;
     double y = 0.0;
 #pragma unroll
-    for (int c = 0; c < 16; ++c) y = fma((double)inv[c], s_vec[part * 16 + c], y);
+    for (int c = 0; c < 16; ++c) y = fma((double)xinv[c], s_vec[part * 16 + c], y);
     const double xi = reduce4(y, sh);
     if (tid < 64) x[64 * I + tid] = xi;
     publish(flags + I);
@@ -739,7 +754,7 @@ __global__ __launch_bounds__(kThreads) void k_trsv_fwd(
 }
 
 // Backward: x = L^{-T} b.  Task t solves block I = T-1-t: s = b_I - sum_{K>I} L_KI^T x_K;
-// x_I = Linv_II^T s.  With acc_out != null the result is also added into acc_out (d += e).
+// x_I = X_II^T s.  With acc_out != null the result is also added into acc_out (d += e).
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_trsv_bwd(
     const R* __restrict__ Lt, const R* __restrict__ Linv, int T, const double* __restrict__ b,
@@ -756,25 +771,37 @@ __global__ __launch_bounds__(kThreads) void k_trsv_bwd(
     const uint32_t t = claim(sync);
     if (t >= (uint32_t)T) break;
     const int I = T - 1 - (int)t;
+    R xinv[16], cur[16], nxt[16];
+    // (X_II^T s)[c] = sum_r X_II[r][c] s[r]; (L_KI^T x_K)[c] = sum_r L_KI[r][c] x_K[r]
+    const R* inv = Linv + (int64_t)I * 4096 + (part * 16) * 64 + c;
+#pragma unroll
+    for (int rr = 0; rr < 16; ++rr) xinv[rr] = inv[rr * 64];
+    if (I < T - 1) {
+      const R* tile = Lt + (int64_t)tile_index(T - 1, I, T) * 4096 + (part * 16) * 64 + c;
+#pragma unroll
+      for (int rr = 0; rr < 16; ++rr) nxt[rr] = tile[rr * 64];
+    }
     double acc = 0.0;
     bool ok = true;
     for (int K = T - 1; K > I; --K) {
-      ok = wait_flag(flags + K, sync, status);
-      if (!ok) break;
-      // (L_KI^T x_K)[c] = sum_r L_KI[r][c] x_K[r]
-      const R* tile = Lt + (int64_t)tile_index(K, I, T) * 4096 + (part * 16) * 64 + c;
+#pragma unroll
+      for (int rr = 0; rr < 16; ++rr) cur[rr] = nxt[rr];
+      if (K - 1 > I) {
+        const R* tile = Lt + (int64_t)tile_index(K - 1, I, T) * 4096 + (part * 16) * 64 + c;
+#pragma unroll
+        for (int rr = 0; rr < 16; ++rr) nxt[rr] = tile[rr * 64];
+      }
+      if (ok) ok = wait_flag(flags + K, sync, status);
       const double* xv = x + 64 * K + part * 16;
 #pragma unroll
-      for (int rr = 0; rr < 16; ++rr) acc = fma((double)tile[rr * 64], xv[rr], acc);
+      for (int rr = 0; rr < 16; ++rr) acc = fma((double)cur[rr], xv[rr], acc);
     }
     const double sum = reduce4(acc, sh);
     if (tid < 64) s_vec[tid] = b[64 * I + tid] - sum;
     __syncthreads();
-    // x_I[c] = sum_r Linv[r][c] s[r]
-    const R* inv = Linv + (int64_t)I * 4096 + (part * 16) * 64 + c;
     double y = 0.0;
 #pragma unroll
-    for (int rr = 0; rr < 16; ++rr) y = fma((double)inv[rr * 64], s_vec[part * 16 + rr], y);
+    for (int rr = 0; rr < 16; ++rr) y = fma((double)xinv[rr], s_vec[part * 16 + rr], y);
     const double xi = reduce4(y, sh);
     if (tid < 64) {
       x[64 * I + tid] = xi;
@@ -786,52 +813,91 @@ __global__ __launch_bounds__(kThreads) void k_trsv_bwd(
   exit_and_reset(sync, flags, T);
 }
 
-// Refinement residual s = g - (H + mu I) d in FP64 (H column-major lower, element type R),
-// one workgroup per 64-row block; per-block ||s||^2 into s_part.
+// Refinement residual s = g - (H + mu I) d in FP64 from the FP32/FP64 column-major lower
+// storage.  Pass 1: one workgroup per lower tile (I, J) writes its two contributions,
+// H_IJ d_J (to rows of block I) and, off the diagonal, H_IJ^T d_I (to rows of block J), into
+// per-tile partials; reads follow the storage's contiguous columns.  Pass 2: one workgroup
+// per block row sums the partials in a fixed order, so the result is deterministic.
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_refine_resid(
-    const R* __restrict__ Hc, int64_t ld, int T, const double* __restrict__ mu_dev,
-    const double* __restrict__ g, const double* __restrict__ d, double* __restrict__ s,
-    double* __restrict__ s_part, const LMState* __restrict__ lm, int gate) {
+__global__ __launch_bounds__(kThreads) void k_symv_tiles(
+    const R* __restrict__ Hc, int64_t ld, int T, const double* __restrict__ d,
+    double* __restrict__ prow, double* __restrict__ pcol, const LMState* __restrict__ lm,
+    int gate) {
   if (gated(lm, gate)) return;
+  __shared__ double sd_col[64];   // d_J
+  __shared__ double sd_row[64];   // d_I
   __shared__ double sh[kThreads];
-  const int I = blockIdx.x;
-  const int tid = threadIdx.x, r = tid & 63, part = tid >> 6;
-  const int64_t row = 64 * (int64_t)I + r;
-  double acc = 0.0;
-  // columns left of the diagonal tile and the diagonal tile: H[row][col] at col*ld + row
-  for (int J = 0; J < I; ++J) {
-    for (int cc = 0; cc < 16; ++cc) {
-      const int64_t col = 64 * (int64_t)J + part * 16 + cc;
-      acc = fma((double)Hc[col * ld + row], d[col], acc);
+  int I = 0, J = 0;
+  {
+    // blockIdx.x enumerates the lower tiles column-major
+    uint32_t t = blockIdx.x, start = 0;
+    int j = 0;
+    while (start + (uint32_t)(T - j) <= t) {
+      start += (uint32_t)(T - j);
+      ++j;
     }
+    J = j;
+    I = j + (int)(t - start);
   }
+  const int tid = threadIdx.x, r = tid & 63, part = tid >> 6;
+  if (tid < 64) {
+    sd_col[tid] = d[64 * J + tid];
+    sd_row[tid] = d[64 * I + tid];
+  }
+  __syncthreads();
+  const R* base = Hc + (int64_t)(64 * J) * ld + 64 * I;   // element (row r, col c) at c*ld + r
+  // rows of block I: sum_c H[r][c] d_J[c]; for the diagonal tile use the lower part only
+  double a = 0.0;
+#pragma unroll 4
   for (int cc = 0; cc < 16; ++cc) {
     const int cl = part * 16 + cc;
-    const int64_t col = 64 * (int64_t)I + cl;
-    const R h = (cl <= r) ? Hc[col * ld + row] : Hc[row * ld + col];
-    acc = fma((double)h, d[col], acc);
+    R h;
+    if (I != J || cl <= r) h = base[(int64_t)cl * ld + r];
+    else h = base[(int64_t)r * ld + cl];
+    a = fma((double)h, sd_col[cl], a);
   }
-  // below the diagonal tile: H[row][col] = H[col][row] stored at row*ld + col
-  for (int J = I + 1; J < T; ++J) {
-    const R* src = Hc + row * ld + 64 * (int64_t)J + part * 16;
-    const double* dv = d + 64 * (int64_t)J + part * 16;
-#pragma unroll
-    for (int cc = 0; cc < 16; ++cc) acc = fma((double)src[cc], dv[cc], acc);
+  const double rowsum = reduce4(a, sh);
+  if (tid < 64) prow[((int64_t)blockIdx.x) * 64 + tid] = rowsum;
+  if (I != J) {
+    // rows of block J: sum_r H[r][c] d_I[r] (column c of the tile is contiguous)
+    const int cl = tid & 63;
+    double b2 = 0.0;
+    const R* col = base + (int64_t)cl * ld + part * 16;
+#pragma unroll 4
+    for (int rr = 0; rr < 16; ++rr) b2 = fma((double)col[rr], sd_row[part * 16 + rr], b2);
+    const double colsum = reduce4(b2, sh);
+    if (tid < 64) pcol[((int64_t)blockIdx.x) * 64 + tid] = colsum;
   }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_symv_combine(
+    int T, const double* __restrict__ mu_dev, const double* __restrict__ g,
+    const double* __restrict__ d, const double* __restrict__ prow,
+    const double* __restrict__ pcol, double* __restrict__ s, double* __restrict__ s_part,
+    const LMState* __restrict__ lm, int gate) {
+  if (gated(lm, gate)) return;
+  __shared__ double sh[kThreads];
+  const int B = blockIdx.x;           // block row
+  const int tid = threadIdx.x, r = tid & 63, part = tid >> 6;
+  // block row B gathers prow of tiles (B, J), J <= B, and pcol of tiles (I, B), I > B
+  double acc = 0.0;
+  for (int J = part; J <= B; J += 4) {
+    const uint32_t ti = (uint32_t)(J * T - (J * (J - 1)) / 2 + (B - J));
+    acc += prow[(int64_t)ti * 64 + r];
+  }
+  const uint32_t cstart = (uint32_t)(B * T - (B * (B - 1)) / 2);
+  for (int I = B + 1 + part; I < T; I += 4) acc += pcol[((int64_t)cstart + (I - B)) * 64 + r];
   const double hd = reduce4(acc, sh);
   double sq = 0.0;
   if (tid < 64) {
-    const double mu = *mu_dev;
-    const double si = g[row] - mu * d[row] - hd;
+    const int64_t row = 64 * (int64_t)B + r;
+    const double si = g[row] - (*mu_dev) * d[row] - hd;
     s[row] = si;
     sq = si * si;
-  }
-  // fixed-order block sum of sq over the first wave
-  if (tid < 64) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) sq += __shfl_down(sq, off, 64);
-    if (tid == 0) s_part[I] = sq;
+    if (tid == 0) s_part[B] = sq;
   }
 }
 
@@ -873,9 +939,14 @@ hipError_t launch_trsv(bool forward, const R* Lt, const R* Linv, int n_pad, cons
 template <typename R>
 hipError_t launch_refine_resid(const R* Hc, int ld, int n_pad, const double* mu_dev,
                                const double* g, const double* d, double* s, double* s_part,
-                               const LMState* lm, int gate, hipStream_t st) {
-  hipLaunchKernelGGL(k_refine_resid<R>, dim3(n_pad / 64), dim3(kThreads), 0, st, Hc, (int64_t)ld,
-                     n_pad / 64, mu_dev, g, d, s, s_part, lm, gate);
+                               double* prow, double* pcol, const LMState* lm, int gate,
+                               hipStream_t st) {
+  const int T = n_pad / 64;
+  const int ntiles = T * (T + 1) / 2;
+  hipLaunchKernelGGL(k_symv_tiles<R>, dim3(ntiles), dim3(kThreads), 0, st, Hc, (int64_t)ld, T, d,
+                     prow, pcol, lm, gate);
+  hipLaunchKernelGGL(k_symv_combine<R>, dim3(T), dim3(kThreads), 0, st, T, mu_dev, g, d, prow,
+                     pcol, s, s_part, lm, gate);
   return hipGetLastError();
 }
 
@@ -897,8 +968,8 @@ hipError_t set_chol_smem_attr() {
                                      double*, SyncArea*, uint32_t*, int32_t*, const LMState*,  \
                                      int, hipStream_t);                                        \
   template hipError_t launch_refine_resid<R>(const R*, int, int, const double*, const double*, \
-                                             const double*, double*, double*, const LMState*,  \
-                                             int, hipStream_t);
+                                             const double*, double*, double*, double*, double*, \
+                                             const LMState*, int, hipStream_t);
 DDC_INST(float)
 DDC_INST(double)
 #undef DDC_INST

@@ -123,7 +123,7 @@ def main():
     t1 = time.perf_counter()
     elapsed = t1 - t0
     timers = {name: ctx.timing(i) for i, name in enumerate(
-        ["cholesky", "predict", "build", "trsv", "trial", "model", "refine"])}
+        ["cholesky", "predict", "build", "trsv", "trial", "model", "refine", "adjoint"])}
     ctx.enable_timing(False)
     infos = step(want_info=True)
     torch.cuda.synchronize()

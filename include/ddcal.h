@@ -188,6 +188,15 @@ ddc_status ddc_calibrate(ddc_ctx* ctx, const ddc_obs* obs, const ddc_sky* sky, c
                          double* jones, const ddc_cal_opts* opts, void* res,
                          ddc_lm_info* info);
 
+/* Gradient of f = ||vis - sum_{k<K} J_k C_k J_k^H||^2 with respect to every cluster's Jones
+ * in the real-pair layout of `jones`: grad[k][p][2e+c] = df/d(Re or Im of (J_{p,k})_e)
+ * (double, [K][N][8]).  A hand-written adjoint kernel: df/dx_k = -2 (sum R G^H + sum R^H Hm)
+ * per station with G = C J_q^H, Hm = J_p C.  cost (HOST, nullable) receives f and makes the
+ * call synchronise.  DDC_MIXED computes the residual and the sums in FP32. */
+ddc_status ddc_cost_gradient(ddc_ctx* ctx, const ddc_obs* obs, int32_t n_clusters,
+                             const void* vis, const void* coh, const double* jones,
+                             int32_t precision, double* grad, double* cost);
+
 /* Kernel timing for measurement.  When enabled, the library brackets each launch of the
  * kernels below with HIP events on the context stream and accumulates, per kernel class,
  * the launch count, the summed durations and the summed algorithmic work of the launches.
@@ -199,7 +208,8 @@ typedef enum {
   DDC_TIMER_TRSV = 3,       /* triangular solves; work = bytes of the factor read */
   DDC_TIMER_TRIAL = 4,      /* trial cost; work = bytes */
   DDC_TIMER_MODEL = 5,      /* model add/subtract and residual; work = bytes */
-  DDC_TIMER_REFINE = 6      /* refinement residual; work = bytes */
+  DDC_TIMER_REFINE = 6,     /* refinement residual; work = bytes */
+  DDC_TIMER_ADJOINT = 7     /* cost adjoint; work = bytes */
 } ddc_timer;
 ddc_status ddc_enable_timing(ddc_ctx* ctx, int32_t on);
 ddc_status ddc_get_timing(ddc_ctx* ctx, int32_t which, int64_t* launches, double* total_ms,

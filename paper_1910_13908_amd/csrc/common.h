@@ -86,6 +86,12 @@ hipError_t launch_trial_cost(const ObsDev& o, const R* y, const R* coh, const do
                              const double* d, double* cost_part, int* nblk, const LMState* lm,
                              hipStream_t st);
 
+// grad[k][s][8] = df/dx of every cluster from the residual res (per-baseline partials in
+// part, [K][16][B]).
+template <typename R>
+hipError_t launch_cost_adjoint(const ObsDev& o, int K, const R* res, const R* coh,
+                               const double* jones, R* part, double* grad, hipStream_t st);
+
 // k_chol.hip
 // Factor H + mu I (mu from mu_dev if non-null); with g != null also y = L^{-1} g.
 template <typename R>

@@ -19,7 +19,7 @@ namespace {
 constexpr int kMaxTiles = 512;                  // n_pad <= 32768 (N <= 4096 stations)
 constexpr size_t kSyncBytes = 1u << 20;
 
-enum Timer { T_CHOL = 0, T_PREDICT, T_BUILD, T_TRSV, T_TRIAL, T_MODEL, T_REFINE, T_COUNT };
+enum Timer { T_CHOL = 0, T_PREDICT, T_BUILD, T_TRSV, T_TRIAL, T_MODEL, T_REFINE, T_ADJOINT, T_COUNT };
 
 struct TimerAcc {
   int64_t launches = 0;
@@ -772,6 +772,58 @@ ddc_status ddc_calibrate(ddc_ctx* c, const ddc_obs* obs, const ddc_sky* sky, con
     return fail(c, DDC_EINVAL, "sky arrays must not be NULL");
   if (opts->lm.precision == DDC_MIXED) return calibrate_impl<float>(c, o, sky, vis, jones, *opts, res, info);
   return calibrate_impl<double>(c, o, sky, vis, jones, *opts, res, info);
+}
+
+}  // extern "C"
+
+namespace {
+template <typename R>
+ddc_status cost_gradient_impl(ddc_ctx* c, const ObsDev& o, int K, const void* vis, const void* coh,
+                              const double* jones, double* grad, double* cost) {
+  const int64_t plane = (int64_t)o.T * o.F * o.B;
+  const int64_t nblk = (plane + 255) / 256;
+  Bump bp;
+  const size_t o_res = bp.take((size_t)8 * plane * sizeof(R));
+  const size_t o_part = bp.take((size_t)K * 16 * o.B * sizeof(R));
+  const size_t o_cp = bp.take((size_t)nblk * sizeof(double));
+  const size_t o_tot = bp.take(64);
+  DDCCK(ensure_ws(c, bp.off));
+  R* res = reinterpret_cast<R*>(c->ws + o_res);
+  R* part = reinterpret_cast<R*>(c->ws + o_part);
+  double* cp = reinterpret_cast<double*>(c->ws + o_cp);
+  double* tot = reinterpret_cast<double*>(c->ws + o_tot);
+  hipStream_t st = c->stream;
+  int nb = 0;
+  const double es = sizeof(R);
+  DDCCK(timed(c, T_MODEL, (double)plane * (16.0 + 8.0 * K) * es, [&] {
+    return launch_add_model<R>(o, 0, K, reinterpret_cast<const R*>(vis), reinterpret_cast<const R*>(coh),
+                               jones, -1.0, res, cp, &nb, st);
+  }));
+  DDCCK(timed(c, T_ADJOINT, (double)plane * 16.0 * K * es, [&] {
+    return launch_cost_adjoint<R>(o, K, res, reinterpret_cast<const R*>(coh), jones, part, grad, st);
+  }));
+  if (cost) {
+    HIPCK(launch_sum(cp, nb, tot, st));
+    HIPCK(hipMemcpyAsync(cost, tot, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCK(hipStreamSynchronize(st));
+  }
+  return DDC_OK;
+}
+}  // namespace
+
+extern "C" {
+
+ddc_status ddc_cost_gradient(ddc_ctx* c, const ddc_obs* obs, int32_t K, const void* vis,
+                             const void* coh, const double* jones, int32_t prec, double* grad,
+                             double* cost) {
+  if (!c) return DDC_EINVAL;
+  (void)hipSetDevice(c->device);
+  ObsDev o;
+  DDCCK(obs_dev(c, obs, o));
+  DDCCK(check_prec(c, prec));
+  if (K < 1 || !vis || !coh || !jones || !grad) return fail(c, DDC_EINVAL, "bad cost_gradient arguments");
+  if (prec == DDC_MIXED) return cost_gradient_impl<float>(c, o, K, vis, coh, jones, grad, cost);
+  return cost_gradient_impl<double>(c, o, K, vis, coh, jones, grad, cost);
 }
 
 ddc_status ddc_enable_timing(ddc_ctx* c, int32_t on) {

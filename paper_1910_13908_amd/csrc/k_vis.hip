@@ -379,6 +379,88 @@ __global__ __launch_bounds__(kThreads) void k_trial_cost(
   if (threadIdx.x == 0) cost_part[blockIdx.x] = s;
 }
 
+
+// ---------------------------------------------------------------------------------------
+// Adjoint of the cost f = ||R||^2, R = V - sum_k J_{p,k} C_k J_{q,k}^H, with respect to every
+// cluster's Jones in the real-pair view: df/dx_k = -2 (Re, Im) of
+//   sum_{p left} R G_k^H + sum_{p right} R^H Hm_k,   G_k = C_k J_{q,k}^H, Hm_k = J_{p,k} C_k.
+// Pass 1: one thread per (baseline, cluster) reduces over T*F into per-baseline partials
+// (the clusters of one baseline tile are neighbouring workgroups, so R is re-read from L2).
+// Pass 2: one workgroup per (station, cluster) sums the partials in a fixed order.
+// ---------------------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_cost_adjoint(
+    const R* __restrict__ res, const R* __restrict__ coh, const double* __restrict__ jones,
+    const int32_t* __restrict__ ant_p, const int32_t* __restrict__ ant_q, int64_t B, int TF,
+    int N, int K, R* __restrict__ part) {
+  const int k = blockIdx.x % K;
+  const int64_t b = (int64_t)(blockIdx.x / K) * kThreads + threadIdx.x;
+  if (b >= B) return;
+  const int64_t plane = (int64_t)TF * B;
+  const int p = ant_p[b], q = ant_q[b];
+  const double* Jk = jones + (int64_t)k * 8 * N;
+  const M2<R> Jp = load_jones<R>(Jk, p);
+  const M2<R> Jq = load_jones<R>(Jk, q);
+  const R* ck = coh + (int64_t)k * 8 * plane;
+  M2<R> zl, zr;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) zl.e[e] = zr.e[e] = {0, 0};
+  for (int tf = 0; tf < TF; ++tf) {
+    const int64_t idx = (int64_t)tf * B + b;
+    const M2<R> C = load_vis(ck, plane, idx);
+    const M2<R> Rr = load_vis(res, plane, idx);
+    const M2<R> G = mmul_bh(C, Jq);
+    const M2<R> Hm = mmul(Jp, C);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int kk = 0; kk < 2; ++kk) {
+        zl.e[i * 2 + kk] = cfmac(Rr.e[i * 2 + 1], G.e[kk * 2 + 1], cfmac(Rr.e[i * 2 + 0], G.e[kk * 2 + 0], zl.e[i * 2 + kk]));
+        zr.e[i * 2 + kk] = cfmaca(Rr.e[1 * 2 + i], Hm.e[1 * 2 + kk], cfmaca(Rr.e[0 * 2 + i], Hm.e[0 * 2 + kk], zr.e[i * 2 + kk]));
+      }
+  }
+  R* out = part + (int64_t)k * 16 * B + b;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    out[(2 * e) * B] = zl.e[e].r;
+    out[(2 * e + 1) * B] = zl.e[e].i;
+    out[(8 + 2 * e) * B] = zr.e[e].r;
+    out[(8 + 2 * e + 1) * B] = zr.e[e].i;
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_adjoint_station(const R* __restrict__ part, int N,
+                                                             int64_t B, double* __restrict__ grad) {
+  __shared__ R red[8][kThreads];
+  const int s = blockIdx.x, k = blockIdx.y, tid = threadIdx.x;
+  const R* pk = part + (int64_t)k * 16 * B;
+  R acc[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) acc[i] = 0;
+  const int64_t b0 = (int64_t)s * (2 * (int64_t)N - s - 1) / 2;
+  for (int j = tid; j < N - 1 - s; j += kThreads) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[i] += pk[(int64_t)i * B + b0 + j];
+  }
+  for (int p = tid; p < s; p += kThreads) {
+    const int64_t b = (int64_t)p * (2 * (int64_t)N - p - 1) / 2 + (s - p - 1);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[i] += pk[(int64_t)(8 + i) * B + b];
+  }
+#pragma unroll
+  for (int i = 0; i < 8; ++i) red[i][tid] = acc[i];
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if (tid < w) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) red[i][tid] += red[i][tid + w];
+    }
+    __syncthreads();
+  }
+  if (tid < 8) grad[((int64_t)k * N + s) * 8 + tid] = -2.0 * (double)red[tid][0];
+}
+
 __global__ __launch_bounds__(kThreads) void k_sum(const double* __restrict__ parts, int n,
                                                   double* __restrict__ out) {
   __shared__ double sh[kThreads / 64];
@@ -437,6 +519,17 @@ hipError_t launch_trial_cost(const ObsDev& o, const R* y, const R* coh, const do
   return hipGetLastError();
 }
 
+
+template <typename R>
+hipError_t launch_cost_adjoint(const ObsDev& o, int K, const R* res, const R* coh,
+                               const double* jones, R* part, double* grad, hipStream_t st) {
+  const unsigned tiles = (unsigned)((o.B + kThreads - 1) / kThreads);
+  hipLaunchKernelGGL(k_cost_adjoint<R>, dim3(tiles * (unsigned)K), dim3(kThreads), 0, st, res, coh,
+                     jones, o.ant_p, o.ant_q, o.B, o.T * o.F, o.N, K, part);
+  hipLaunchKernelGGL(k_adjoint_station<R>, dim3(o.N, K), dim3(kThreads), 0, st, part, o.N, o.B, grad);
+  return hipGetLastError();
+}
+
 #define DDC_INST(R)                                                                          \
   template hipError_t launch_add_model<R>(const ObsDev&, int, int, const R*, const R*,        \
                                           const double*, double, R*, double*, int*,           \
@@ -448,7 +541,9 @@ hipError_t launch_trial_cost(const ObsDev& o, const R* y, const R* coh, const do
                                             double*, const LMState*, hipStream_t);            \
   template hipError_t launch_trial_cost<R>(const ObsDev&, const R*, const R*, const double*,  \
                                            const double*, double*, int*, const LMState*,      \
-                                           hipStream_t);
+                                           hipStream_t);                                       \
+  template hipError_t launch_cost_adjoint<R>(const ObsDev&, int, const R*, const R*,          \
+                                             const double*, R*, double*, hipStream_t);
 DDC_INST(float)
 DDC_INST(double)
 #undef DDC_INST

@@ -28,12 +28,13 @@ FP64 = 0
 MIXED = 1
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOTPD, ENONFINITE, ETIMEOUT = 0, -1, -2, -3, -4, -5, -6
-TIMER_CHOLESKY, TIMER_PREDICT, TIMER_BUILD, TIMER_TRSV, TIMER_TRIAL, TIMER_MODEL, TIMER_REFINE = range(7)
+(TIMER_CHOLESKY, TIMER_PREDICT, TIMER_BUILD, TIMER_TRSV, TIMER_TRIAL, TIMER_MODEL, TIMER_REFINE,
+ TIMER_ADJOINT) = range(8)
 
 EXPORTS = ("ddc_default_lm_opts", "ddc_create", "ddc_destroy", "ddc_set_stream", "ddc_last_error",
            "ddc_workspace_bytes", "ddc_predict", "ddc_residual", "ddc_add_model",
            "ddc_build_normal_eq", "ddc_damped_solve", "ddc_lm_solve", "ddc_calibrate",
-           "ddc_enable_timing", "ddc_get_timing")
+           "ddc_cost_gradient", "ddc_enable_timing", "ddc_get_timing")
 
 
 class Obs(ct.Structure):
@@ -91,6 +92,8 @@ _lib.ddc_lm_solve.argtypes = [_vp, ct.POINTER(Obs), _vp, _vp, _vp, ct.POINTER(LM
                               ct.POINTER(LMState), ct.POINTER(LMInfo)]
 _lib.ddc_calibrate.argtypes = [_vp, ct.POINTER(Obs), ct.POINTER(Sky), _vp, _vp, ct.POINTER(CalOpts),
                                _vp, ct.POINTER(LMInfo)]
+_lib.ddc_cost_gradient.argtypes = [_vp, ct.POINTER(Obs), ct.c_int32, _vp, _vp, _vp, ct.c_int32, _vp,
+                                   ct.POINTER(ct.c_double)]
 _lib.ddc_enable_timing.argtypes = [_vp, ct.c_int32]
 _lib.ddc_get_timing.argtypes = [_vp, ct.c_int32, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_double),
                                 ct.POINTER(ct.c_double)]
@@ -221,6 +224,16 @@ class Context:
         if not want_info:
             return None
         return [[infos[e * sky.K + k] for k in range(sky.K)] for e in range(n_sweeps)]
+
+    def cost_gradient(self, obs, K, vis, coh, jones, precision, grad=None, want_cost=True):
+        """f and df/d(jones) ([K, N, 8] float64) from the adjoint kernel."""
+        if grad is None:
+            grad = self._torch.empty_like(jones)
+        cost = ct.c_double(0.0)
+        self._bind()
+        self._check(_lib.ddc_cost_gradient(self.h, ct.byref(obs.c), K, _ptr(vis), _ptr(coh), _ptr(jones),
+                                           precision, _ptr(grad), ct.byref(cost) if want_cost else None))
+        return (cost.value if want_cost else None), grad
 
     def enable_timing(self, on=True):
         self._check(_lib.ddc_enable_timing(self.h, 1 if on else 0))

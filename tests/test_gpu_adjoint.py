@@ -1,0 +1,87 @@
+"""Adjoint kernel vs the oracle gradient and vs central finite differences; autograd and
+L-BFGS on top of it."""
+import numpy as np
+import pytest
+
+from oracle import rime, adjoint as oadj, lm as olm, align
+from paper_1910_13908_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_1910_13908_amd import ddcal as dd
+    assert torch.cuda.is_available()
+    ctx = dd.Context(0)
+    yield dd, ctx
+    ctx.close()
+
+
+def _problem(dd, ctx, prec, cfg, seed):
+    import torch
+    ob = synth.make_obs(cfg, seed=seed)
+    V, C = rime.make_vis(ob)
+    dt = torch.float32 if prec == dd.MIXED else torch.float64
+    obs, sky = dd.device_obs(ob), dd.device_sky(ob)
+    coh = ctx.predict(obs, sky, prec)
+    Vd = torch.as_tensor(dd.planes(V), dtype=dt, device="cuda").contiguous()
+    return ob, V, C, obs, coh, Vd
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
+def test_gradient_vs_oracle(env, prec):
+    import torch
+    dd, ctx = env
+    cfg = synth.ObsConfig(14, 3, 4, 3, (145e6, 155e6), jones_amp=0.2, polarised=True)
+    ob, V, C, obs, coh, Vd = _problem(dd, ctx, prec, cfg, 21)
+    rng = np.random.default_rng(22)
+    J = ob.jones_true + 0.05 * (rng.normal(size=ob.jones_true.shape) + 1j * rng.normal(size=ob.jones_true.shape))
+    f, g = oadj.cost_and_gradient(V, C, J, ob.ant_p, ob.ant_q)
+    Jd = torch.as_tensor(dd.jones_real(J), device="cuda").contiguous()
+    fg, gg = ctx.cost_gradient(obs, ob.K, Vd, coh, Jd, prec)
+    gg = gg.cpu().numpy()
+    tol = 1e-10 if prec == 0 else 1e-4
+    assert np.linalg.norm(gg - g) <= tol * np.linalg.norm(g), np.linalg.norm(gg - g) / np.linalg.norm(g)
+    assert abs(fg - f) <= (1e-11 if prec == 0 else 1e-5) * f
+
+
+def test_gradient_vs_finite_differences_fp64(env):
+    import torch
+    dd, ctx = env
+    cfg = synth.ObsConfig(10, 2, 3, 2, (150e6,), jones_amp=0.2)
+    ob, V, C, obs, coh, Vd = _problem(dd, ctx, 0, cfg, 23)
+    rng = np.random.default_rng(24)
+    J = ob.jones_true + 0.05 * (rng.normal(size=ob.jones_true.shape) + 1j * rng.normal(size=ob.jones_true.shape))
+    x = torch.as_tensor(dd.jones_real(J), device="cuda").contiguous()
+    _, g = ctx.cost_gradient(obs, ob.K, Vd, coh, x, 0)
+    g = g.cpu().numpy()
+    h = 1e-6
+    for idx in [(0, 0, 0), (0, 3, 5), (1, 7, 2), (1, 9, 7), (0, 5, 1)]:
+        xp = x.clone(); xp[idx] += h
+        xm = x.clone(); xm[idx] -= h
+        fp = ctx.residual(obs, ob.K, Vd, coh, xp, 0, None)
+        fm = ctx.residual(obs, ob.K, Vd, coh, xm, 0, None)
+        fd = (fp - fm) / (2 * h)
+        assert abs(fd - g[idx]) <= 1e-6 * max(1.0, np.max(np.abs(g))), (idx, fd, g[idx])
+
+
+def test_autograd_and_lbfgs_reach_the_lm_cost(env):
+    import torch
+    from paper_1910_13908_amd import autograd as ag
+    dd, ctx = env
+    cfg = synth.ObsConfig(16, 2, 4, 4, (150e6,), jones_amp=0.1)
+    ob, V, C, obs, coh, Vd = _problem(dd, ctx, 0, cfg, 25)
+    prob = ag.Problem(ctx, obs, ob.K, Vd, coh, dd.FP64)
+    x = torch.as_tensor(dd.jones_real(synth.identity_jones(ob.K, ob.N)), device="cuda").contiguous()
+    x.requires_grad_(True)
+    f = ag.calibration_cost(x, prob)
+    f.backward()
+    _, g = ctx.cost_gradient(obs, ob.K, Vd, coh, x.detach().contiguous(), 0)
+    assert torch.equal(x.grad, g)
+    Jl, costs = ag.lbfgs_calibrate(prob, x.detach(), n_iter=150)
+    Jo, Ro, io, _ = olm.calibrate(V, C, synth.identity_jones(ob.K, ob.N), ob.ant_p, ob.ant_q, n_sweeps=6, n_lm=10)
+    f_lm = rime.cost(Ro)
+    assert all(b <= a * (1 + 1e-12) for a, b in zip(costs, costs[1:]))
+    assert costs[-1] <= f_lm * (1 + 1e-6), (costs[-1], f_lm)

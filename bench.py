@@ -77,7 +77,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU layout is "
-              "described in DESIGN.md but not built", file=sys.stderr)
+              "designed but not built", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_1910_13908_amd import synth, ddcal as dd

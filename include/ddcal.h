@@ -197,6 +197,41 @@ ddc_status ddc_cost_gradient(ddc_ctx* ctx, const ddc_obs* obs, int32_t n_cluster
                              const void* vis, const void* coh, const double* jones,
                              int32_t precision, double* grad, double* cost);
 
+/* ---------------------------------------------------------------------------------------
+ * Serving: continuous batching of whole calibrations (one request = one ddc_calibrate, e.g.
+ * one frequency band; the paper's setting of many more bands than nodes, abstract and
+ * Section 1).  Requests are admitted in arrival order when a slot (a context with its own
+ * stream) is free and the request's workspace footprint fits in a free range of the server's
+ * HBM arena; admitted requests run concurrently, and the predict work of requests admitted
+ * together is fused into one persistent batched launch.  Every reduction in the path has a
+ * fixed order, so a request's result is bitwise the same alone and in the mix.
+ * ------------------------------------------------------------------------------------- */
+typedef struct ddc_server ddc_server;
+
+/* Bytes of workspace ddc_calibrate (and the server) needs for this problem; -1 if invalid. */
+int64_t ddc_calibrate_footprint(const ddc_obs* obs, int32_t n_clusters, int32_t n_sweeps,
+                                int32_t precision);
+/* Server on `device` with n_slots concurrent solves (1..64) and an HBM arena of
+ * hbm_budget_bytes allocated up front (DDC_ENOMEM if that fails). */
+ddc_status ddc_server_create(ddc_server** out, int32_t device, int32_t n_slots,
+                             int64_t hbm_budget_bytes);
+/* Finishes every submitted request, then releases everything. */
+ddc_status ddc_server_destroy(ddc_server* server);
+/* Queue one calibration.  All device arrays of obs, sky, vis and jones must stay valid and
+ * unmodified until ddc_server_wait returns for it; the host cluster offsets and the options
+ * are copied.  DDC_ENOMEM if the request can never fit the arena. */
+ddc_status ddc_server_submit(ddc_server* server, const ddc_obs* obs, const ddc_sky* sky,
+                             const void* vis, double* jones, const ddc_cal_opts* opts,
+                             int64_t* request_id);
+/* Block until the request is done; info (HOST, nullable) receives [n_sweeps][K] reports,
+ * latency_s the time from submit to completion, queue_s the time from submit to admission.
+ * Returns the request's own status (its message via ddc_server_last_error). */
+ddc_status ddc_server_wait(ddc_server* server, int64_t request_id, ddc_lm_info* info,
+                           double* latency_s, double* queue_s);
+ddc_status ddc_server_stats(ddc_server* server, int64_t* completed, int32_t* max_running,
+                            int64_t* peak_arena_bytes);
+const char* ddc_server_last_error(const ddc_server* server);
+
 /* Kernel timing for measurement.  When enabled, the library brackets each launch of the
  * kernels below with HIP events on the context stream and accumulates, per kernel class,
  * the launch count, the summed durations and the summed algorithmic work of the launches.

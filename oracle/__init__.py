@@ -20,7 +20,7 @@ The paper (Sections 2 and 3) fixes only the problem dimensions: N stations, N(N-
 baselines, sources grouped into clusters with one calibration solution per cluster.
 Everything else follows the textbook radio-interferometric measurement equation
 (Hamaker, Bregman & Sault 1996) and Levenberg-Marquardt as in Madsen, Nielsen & Tingleff
-(2004), Algorithm 3.16; the readings taken where both are silent are listed in the design doc.
+(2004), Algorithm 3.16; where both are silent, each module states the reading it takes.
 
 Parity status: every function here is pinned by ``tests/test_oracle_*.py`` (closed forms,
 invariants, finite differences, brute force at tiny sizes, exact recovery, chi-square

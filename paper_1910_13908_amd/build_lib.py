@@ -14,10 +14,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libddcal.so")
-SOURCES = ["ddcal.cpp", "k_predict.hip", "k_vis.hip", "k_chol.hip", "k_lm.hip"]
+SOURCES = ["ddcal.cpp", "server.cpp", "k_predict.hip", "k_vis.hip", "k_chol.hip", "k_lm.hip"]
 ARCH = os.environ.get("DDC_OFFLOAD_ARCH", "gfx950")
 
-# Packed FP32 instructions are kept out of the generated code (see DESIGN.md).
+# Packed FP32 instructions are kept out of the generated code.
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

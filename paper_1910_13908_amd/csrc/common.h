@@ -62,7 +62,40 @@ struct ObsDev {
   const int32_t* ant_q;
 };
 
+// One solve's predict, as a self-contained descriptor (also the unit of the batched launch).
+struct PredictJob {
+  const double *u, *v, *w, *freq, *l, *m, *I, *Q, *U, *V;
+  const int32_t* offs;      // device [K+1]
+  int64_t B, plane;         // plane = T*F*B
+  int T, F, K, pad;
+  void* coh;                // [K][8][T][F][B] of the element type
+  int64_t first_block;      // offset of this job in the batch's flattened block list
+};
+
+inline PredictJob make_predict_job(const ObsDev& o, int K, const int32_t* offs_dev,
+                                   const double* l, const double* m, const double* I,
+                                   const double* Q, const double* U, const double* V,
+                                   void* coh) {
+  PredictJob j;
+  j.u = o.u; j.v = o.v; j.w = o.w; j.freq = o.freq;
+  j.l = l; j.m = m; j.I = I; j.Q = Q; j.U = U; j.V = V;
+  j.offs = offs_dev;
+  j.B = o.B;
+  j.plane = (int64_t)o.T * o.F * o.B;
+  j.T = o.T; j.F = o.F; j.K = K; j.pad = 0;
+  j.coh = coh;
+  j.first_block = 0;
+  return j;
+}
+
+inline int64_t predict_blocks(const PredictJob& j) {
+  return (j.B + 255) / 256 * (int64_t)j.T * j.F * j.K;
+}
+
 // k_predict.hip
+template <typename R>
+hipError_t launch_predict_batch(const PredictJob* jobs_dev, int njobs, int64_t total_blocks,
+                                int grid, hipStream_t st);
 template <typename R>
 hipError_t launch_predict(const ObsDev& o, int K, const int32_t* offs_dev, const int32_t* offs_host,
                           const double* l, const double* m, const double* I, const double* Q,

@@ -4,6 +4,7 @@
 // codes with a message kept in the context.
 #include "../../include/ddcal.h"
 #include "common.h"
+#include "host_internal.h"
 
 #include <cmath>
 #include <cstdarg>
@@ -43,10 +44,11 @@ struct ddc_ctx {
   std::string err;
   char* ws = nullptr;
   size_t ws_bytes = 0;
+  bool ws_external = false;      // workspace lent by a server arena (not owned, never grown)
   char* sync = nullptr;          // fixed region: LM state, sync areas, flags (zeroed once)
   int tab_N = 0;
   int32_t* ant = nullptr;        // [2][B] canonical baseline table
-  size_t h_off = (size_t)-1;     // matrix storage initialised for (offset, n_pad, n, elem size)
+  const void* h_ptr = nullptr;   // matrix storage initialised for (address, n_pad, n, elem size)
   int h_npad = -1, h_n = -1, h_es = -1;
   bool timing = false;
   std::vector<Pending> pending;
@@ -143,11 +145,13 @@ struct Bump {
 
 ddc_status ensure_ws(ddc_ctx* c, size_t bytes) {
   if (bytes <= c->ws_bytes) return DDC_OK;
+  if (c->ws_external)
+    return fail(c, DDC_ENOMEM, "lent workspace of %zu bytes is smaller than the %zu needed", c->ws_bytes, bytes);
   HIPCK(hipStreamSynchronize(c->stream));
-  if (c->ws) HIPCK(hipFree(c->ws));
+  if (c->ws && !c->ws_external) HIPCK(hipFree(c->ws));
   c->ws = nullptr;
   c->ws_bytes = 0;
-  c->h_off = (size_t)-1;
+  c->h_ptr = nullptr;
   const size_t want = align_up(bytes + bytes / 8, 1 << 20);
   if (hipMalloc(&c->ws, want) != hipSuccess) {
     (void)hipGetLastError();
@@ -265,10 +269,10 @@ void bind_solve(ddc_ctx* c, SolveBufs& b, const std::vector<size_t>& o) {
 // shape changed; builds overwrite only the 8N x 8N lower part afterwards.
 template <typename R>
 ddc_status prepare_matrix(ddc_ctx* c, SolveBufs& b) {
-  if (c->h_off == b.h_off && c->h_npad == b.n_pad && c->h_n == b.n && c->h_es == (int)sizeof(R))
+  if (c->h_ptr == b.Hc && c->h_npad == b.n_pad && c->h_n == b.n && c->h_es == (int)sizeof(R))
     return DDC_OK;
   HIPCK(launch_init_matrix<R>(reinterpret_cast<R*>(b.Hc), b.ld, b.n, c->stream));
-  c->h_off = b.h_off;
+  c->h_ptr = b.Hc;
   c->h_npad = b.n_pad;
   c->h_n = b.n;
   c->h_es = (int)sizeof(R);
@@ -416,7 +420,7 @@ ddc_status ddc_destroy(ddc_ctx* c) {
     (void)hipEventDestroy(p.b);
   }
   for (auto e : c->pool) (void)hipEventDestroy(e);
-  if (c->ws) (void)hipFree(c->ws);
+  if (c->ws && !c->ws_external) (void)hipFree(c->ws);
   if (c->ant) (void)hipFree(c->ant);
   if (c->sync) (void)hipFree(c->sync);
   delete c;
@@ -596,7 +600,7 @@ ddc_status damped_solve_impl(ddc_ctx* c, int n, const void* H, const void* g, do
   bind_solve(c, b, offs);
   hipStream_t st = c->stream;
   // the caller's matrix becomes the column-major lower storage: row r of H is column r
-  c->h_off = (size_t)-1;
+  c->h_ptr = nullptr;
   HIPCK(launch_init_matrix<R>(reinterpret_cast<R*>(b.Hc), b.ld, n, st));
   HIPCK(hipMemcpy2DAsync(b.Hc, (size_t)b.ld * sizeof(R), H, (size_t)n * sizeof(R),
                          (size_t)n * sizeof(R), (size_t)n, hipMemcpyDeviceToDevice, st));
@@ -684,37 +688,77 @@ ddc_status ddc_lm_solve(ddc_ctx* c, const ddc_obs* obs, const void* y, const voi
 }  // extern "C"
 
 namespace {
-template <typename R>
-ddc_status calibrate_impl(ddc_ctx* c, const ObsDev& o, const ddc_sky* sky, const void* vis,
-                          double* jones, const ddc_cal_opts& opt, void* res, ddc_lm_info* info) {
-  const int K = sky->n_clusters;
+
+// Workspace layout of one calibration (shared by ddc_calibrate and the server's footprint).
+struct CalLayout {
+  std::vector<size_t> solve_offs;
+  size_t o_coh, o_R, o_Y, o_off, o_info, total;
+};
+
+CalLayout layout_calibrate(const ObsDev& o, int K, int n_sweeps, size_t es, SolveBufs& b) {
+  CalLayout L;
   const int64_t plane = (int64_t)o.T * o.F * o.B;
   Bump bp;
+  layout_solve(bp, b, 8 * o.N, es, o.B, (o.B + 255) / 256, L.solve_offs);
+  L.o_coh = bp.take((size_t)K * 8 * plane * es);
+  L.o_R = bp.take((size_t)8 * plane * es);
+  L.o_Y = bp.take((size_t)8 * plane * es);
+  L.o_off = bp.take((size_t)(K + 1) * sizeof(int32_t));
+  const int n_info = n_sweeps * K;
+  L.o_info = bp.take((size_t)(n_info > 0 ? n_info : 1) * sizeof(LMState));
+  L.total = bp.off;
+  return L;
+}
+
+}  // namespace
+
+namespace ddc {
+namespace host {
+
+int64_t calibrate_footprint(const ObsDev& o, int K, int n_sweeps, int prec) {
   SolveBufs b;
-  std::vector<size_t> offs;
-  layout_solve(bp, b, 8 * o.N, sizeof(R), o.B, (o.B + 255) / 256, offs);
-  const size_t o_coh = bp.take((size_t)K * 8 * plane * sizeof(R));
-  const size_t o_R = bp.take((size_t)8 * plane * sizeof(R));
-  const size_t o_Y = bp.take((size_t)8 * plane * sizeof(R));
-  const size_t o_off = bp.take((size_t)(K + 1) * sizeof(int32_t));
-  const int n_info = opt.n_sweeps * K;
-  const size_t o_info = bp.take((size_t)(n_info > 0 ? n_info : 1) * sizeof(LMState));
-  DDCCK(ensure_ws(c, bp.off));
-  bind_solve(c, b, offs);
-  DDCCK(prepare_matrix<R>(c, b));
-  R* coh = reinterpret_cast<R*>(c->ws + o_coh);
-  R* Rb = reinterpret_cast<R*>(c->ws + o_R);
-  R* Yb = reinterpret_cast<R*>(c->ws + o_Y);
-  int32_t* doffs = reinterpret_cast<int32_t*>(c->ws + o_off);
-  LMState* dinfo = reinterpret_cast<LMState*>(c->ws + o_info);
+  return (int64_t)layout_calibrate(o, K, n_sweeps, esize(prec), b).total;
+}
+
+ddc_status prepare_calibrate(ddc_ctx* c, const ObsDev& o, const ddc_sky* sky, int n_sweeps,
+                             int prec, CalBufs& cb) {
+  const int K = sky->n_clusters;
+  SolveBufs b;
+  const CalLayout L = layout_calibrate(o, K, n_sweeps, esize(prec), b);
+  DDCCK(ensure_ws(c, L.total));
+  bind_solve(c, b, L.solve_offs);
+  if (prec == DDC_MIXED) DDCCK(prepare_matrix<float>(c, b));
+  else DDCCK(prepare_matrix<double>(c, b));
+  cb.solve = new SolveBufs(b);
+  cb.coh = c->ws + L.o_coh;
+  cb.Rb = c->ws + L.o_R;
+  cb.Yb = c->ws + L.o_Y;
+  cb.doffs = reinterpret_cast<int32_t*>(c->ws + L.o_off);
+  cb.dinfo = reinterpret_cast<LMState*>(c->ws + L.o_info);
+  cb.n_info = n_sweeps * K;
+  cb.K = K;
+  cb.prec = prec;
+  cb.offs_host.assign(sky->cluster_offset, sky->cluster_offset + K + 1);
+  HIPCK(hipMemcpyAsync(cb.doffs, cb.offs_host.data(), (K + 1) * sizeof(int32_t),
+                       hipMemcpyHostToDevice, c->stream));
+  return DDC_OK;
+}
+
+void release_calibrate(CalBufs& cb) {
+  delete reinterpret_cast<SolveBufs*>(cb.solve);
+  cb.solve = nullptr;
+}
+
+template <typename R>
+ddc_status enqueue_sage_t(ddc_ctx* c, const ObsDev& o, const void* vis, double* jones,
+                          const ddc_cal_opts& opt, CalBufs& cb) {
+  const int K = cb.K;
+  const int64_t plane = (int64_t)o.T * o.F * o.B;
+  SolveBufs& b = *reinterpret_cast<SolveBufs*>(cb.solve);
+  R* coh = reinterpret_cast<R*>(cb.coh);
+  R* Rb = reinterpret_cast<R*>(cb.Rb);
+  R* Yb = reinterpret_cast<R*>(cb.Yb);
   hipStream_t st = c->stream;
-  HIPCK(hipMemcpyAsync(doffs, sky->cluster_offset, (K + 1) * sizeof(int32_t), hipMemcpyHostToDevice, st));
-  HIPCK(hipStreamSynchronize(st));
-  const double terms = (double)sky->cluster_offset[K] * plane;
-  DDCCK(timed(c, T_PREDICT, terms, [&] {
-    return launch_predict<R>(o, K, doffs, sky->cluster_offset, sky->l, sky->m, sky->I, sky->Q,
-                             sky->U, sky->V, coh, st);
-  }));
   const double es = sizeof(R);
   DDCCK(timed(c, T_MODEL, (double)plane * (16.0 + 8.0 * K) * es, [&] {
     return launch_add_model<R>(o, 0, K, reinterpret_cast<const R*>(vis), coh, jones, -1.0, Rb,
@@ -731,21 +775,64 @@ ddc_status calibrate_impl(ddc_ctx* c, const ObsDev& o, const ddc_sky* sky, const
       DDCCK(timed(c, T_MODEL, (double)plane * 24.0 * es, [&] {
         return launch_add_model<R>(o, k, k + 1, Yb, coh, jones, -1.0, Rb, nullptr, nullptr, st);
       }));
-      HIPCK(launch_copy_state(c->lm(), dinfo + e * K + k, st));
+      HIPCK(launch_copy_state(c->lm(), cb.dinfo + e * K + k, st));
     }
   }
-  if (res) HIPCK(hipMemcpyAsync(res, Rb, (size_t)8 * plane * sizeof(R), hipMemcpyDeviceToDevice, st));
-  if (info && n_info > 0) {
-    std::vector<LMState> h(n_info);
-    HIPCK(hipMemcpyAsync(h.data(), dinfo, n_info * sizeof(LMState), hipMemcpyDeviceToHost, st));
-    HIPCK(hipStreamSynchronize(st));
-    bool to = false;
-    for (int i = 0; i < n_info; ++i) {
-      fill_info(h[i], info + i);
-      to = to || h[i].timeout || (h[i].notpd & 2);
-    }
-    if (to) return fail(c, DDC_ETIMEOUT, "an inter-workgroup wait timed out");
+  return DDC_OK;
+}
+
+ddc_status enqueue_sage(ddc_ctx* c, const ObsDev& o, const void* vis, double* jones,
+                        const ddc_cal_opts& opt, CalBufs& cb) {
+  if (cb.prec == DDC_MIXED) return enqueue_sage_t<float>(c, o, vis, jones, opt, cb);
+  return enqueue_sage_t<double>(c, o, vis, jones, opt, cb);
+}
+
+ddc_status collect_infos(ddc_ctx* c, CalBufs& cb, ddc_lm_info* info) {
+  if (!info || cb.n_info <= 0) return DDC_OK;
+  std::vector<LMState> h(cb.n_info);
+  HIPCK(hipMemcpyAsync(h.data(), cb.dinfo, cb.n_info * sizeof(LMState), hipMemcpyDeviceToHost, c->stream));
+  HIPCK(hipStreamSynchronize(c->stream));
+  bool to = false;
+  for (int i = 0; i < cb.n_info; ++i) {
+    fill_info(h[i], info + i);
+    to = to || h[i].timeout || (h[i].notpd & 2);
   }
+  if (to) return fail(c, DDC_ETIMEOUT, "an inter-workgroup wait timed out");
+  return DDC_OK;
+}
+
+ddc_status ctx_obs(ddc_ctx* c, const ddc_obs* obs, ObsDev& o) { return obs_dev(c, obs, o); }
+hipStream_t ctx_stream(ddc_ctx* c) { return c->stream; }
+void ctx_lend_workspace(ddc_ctx* c, void* ws, size_t bytes) {
+  c->ws = reinterpret_cast<char*>(ws);
+  c->ws_bytes = bytes;
+  c->ws_external = ws != nullptr;
+  c->h_ptr = nullptr;
+}
+const char* ctx_error(ddc_ctx* c) { return c->err.c_str(); }
+
+}  // namespace host
+}  // namespace ddc
+
+namespace {
+template <typename R>
+ddc_status calibrate_impl(ddc_ctx* c, const ObsDev& o, const ddc_sky* sky, const void* vis,
+                          double* jones, const ddc_cal_opts& opt, void* res, ddc_lm_info* info) {
+  using namespace ddc::host;
+  const int K = sky->n_clusters;
+  const int64_t plane = (int64_t)o.T * o.F * o.B;
+  CalBufs cb;
+  DDCCK(prepare_calibrate(c, o, sky, opt.n_sweeps, opt.lm.precision, cb));
+  struct Guard { CalBufs& cb; ~Guard() { release_calibrate(cb); } } guard{cb};
+  hipStream_t st = c->stream;
+  const double terms = (double)sky->cluster_offset[K] * plane;
+  DDCCK(timed(c, T_PREDICT, terms, [&] {
+    return launch_predict<R>(o, K, cb.doffs, sky->cluster_offset, sky->l, sky->m, sky->I, sky->Q,
+                             sky->U, sky->V, reinterpret_cast<R*>(cb.coh), st);
+  }));
+  DDCCK(enqueue_sage(c, o, vis, jones, opt, cb));
+  if (res) HIPCK(hipMemcpyAsync(res, cb.Rb, (size_t)8 * plane * sizeof(R), hipMemcpyDeviceToDevice, st));
+  if (info) DDCCK(collect_infos(c, cb, info));
   return DDC_OK;
 }
 }  // namespace

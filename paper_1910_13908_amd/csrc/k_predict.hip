@@ -13,6 +13,8 @@
 // take the Stokes-I-only inner loop (two FMAs per term instead of eight).
 #include "common.h"
 
+#include <algorithm>
+
 namespace ddc {
 namespace {
 
@@ -28,30 +30,27 @@ __device__ __forceinline__ void sincos_turns(double frac, double& s, double& c) 
   sincospi(2.0 * frac, &s, &c);
 }
 
+struct PredictShared {
+  double l[kThreads], m[kThreads], n[kThreads];
+  double I[kThreads], Q[kThreads], U[kThreads], V[kThreads];
+};
+
+// One 256-baseline tile at one (timeslot, channel) of one cluster.
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_predict(
-    const double* __restrict__ u, const double* __restrict__ v, const double* __restrict__ w,
-    const double* __restrict__ freq, const double* __restrict__ sl, const double* __restrict__ sm,
-    const double* __restrict__ sI, const double* __restrict__ sQ, const double* __restrict__ sU,
-    const double* __restrict__ sV, const int32_t* __restrict__ offs, int64_t B, int F,
-    int64_t plane, R* __restrict__ coh) {
-  __shared__ double s_l[kThreads], s_m[kThreads], s_n[kThreads];
-  __shared__ double s_I[kThreads], s_Q[kThreads], s_U[kThreads], s_V[kThreads];
-
+__device__ __forceinline__ void predict_tile(const PredictJob& j, int64_t btile, int tf, int k,
+                                             PredictShared& sh) {
   const int tid = threadIdx.x;
-  const int64_t b = (int64_t)blockIdx.x * kThreads + tid;
-  const int tf = blockIdx.y;
-  const int t = tf / F, f = tf % F;
-  const int k = blockIdx.z;
-  const int s0 = offs[k], s1 = offs[k + 1];
+  const int64_t b = btile * kThreads + tid;
+  const int t = tf / j.F, f = tf % j.F;
+  const int s0 = j.offs[k], s1 = j.offs[k + 1];
 
-  const double scale = freq[f] / kCLight;
+  const double scale = j.freq[f] / kCLight;
   double uu = 0.0, vv = 0.0, ww = 0.0;
-  if (b < B) {
-    const int64_t i = (int64_t)t * B + b;
-    uu = u[i] * scale;
-    vv = v[i] * scale;
-    ww = w[i] * scale;
+  if (b < j.B) {
+    const int64_t i = (int64_t)t * j.B + b;
+    uu = j.u[i] * scale;
+    vv = j.v[i] * scale;
+    ww = j.w[i] * scale;
   }
   // accumulators: sum I e, sum Q e, sum U e, sum V e with e = exp(-2 pi i phi)
   R iR = 0, iI = 0, qR = 0, qI = 0, uR = 0, uI = 0, vR = 0, vI = 0;
@@ -61,37 +60,37 @@ __global__ __launch_bounds__(kThreads) void k_predict(
     __syncthreads();
     int pol = 0;
     if (tid < n) {
-      const double l = sl[c0 + tid], m = sm[c0 + tid];
+      const double l = j.l[c0 + tid], m = j.m[c0 + tid];
       const double r2 = l * l + m * m;
-      s_l[tid] = l;
-      s_m[tid] = m;
-      s_n[tid] = -r2 / (1.0 + sqrt(1.0 - r2));       // n - 1 without cancellation
-      s_I[tid] = sI[c0 + tid];
-      const double q = sQ[c0 + tid], uu_ = sU[c0 + tid], vv_ = sV[c0 + tid];
-      s_Q[tid] = q;
-      s_U[tid] = uu_;
-      s_V[tid] = vv_;
+      sh.l[tid] = l;
+      sh.m[tid] = m;
+      sh.n[tid] = -r2 / (1.0 + sqrt(1.0 - r2));       // n - 1 without cancellation
+      sh.I[tid] = j.I[c0 + tid];
+      const double q = j.Q[c0 + tid], uu_ = j.U[c0 + tid], vv_ = j.V[c0 + tid];
+      sh.Q[tid] = q;
+      sh.U[tid] = uu_;
+      sh.V[tid] = vv_;
       pol = (q != 0.0) | (uu_ != 0.0) | (vv_ != 0.0);
     }
     pol = __syncthreads_or(pol);
-    if (b < B) {
+    if (b < j.B) {
       if (!pol) {
-        for (int j = 0; j < n; ++j) {
-          const double ph = fma(uu, s_l[j], fma(vv, s_m[j], ww * s_n[j]));
+        for (int s = 0; s < n; ++s) {
+          const double ph = fma(uu, sh.l[s], fma(vv, sh.m[s], ww * sh.n[s]));
           const double fr = ph - rint(ph);
           R sn, cs;
           sincos_turns(fr, sn, cs);
-          const R I = (R)s_I[j];
+          const R I = (R)sh.I[s];
           iR = fma(I, cs, iR);
           iI = fma(-I, sn, iI);
         }
       } else {
-        for (int j = 0; j < n; ++j) {
-          const double ph = fma(uu, s_l[j], fma(vv, s_m[j], ww * s_n[j]));
+        for (int s = 0; s < n; ++s) {
+          const double ph = fma(uu, sh.l[s], fma(vv, sh.m[s], ww * sh.n[s]));
           const double fr = ph - rint(ph);
           R sn, cs;
           sincos_turns(fr, sn, cs);
-          const R I = (R)s_I[j], Q = (R)s_Q[j], U = (R)s_U[j], V = (R)s_V[j];
+          const R I = (R)sh.I[s], Q = (R)sh.Q[s], U = (R)sh.U[s], V = (R)sh.V[s];
           iR = fma(I, cs, iR);
           iI = fma(-I, sn, iI);
           qR = fma(Q, cs, qR);
@@ -104,9 +103,10 @@ __global__ __launch_bounds__(kThreads) void k_predict(
       }
     }
   }
-  if (b < B) {
+  if (b < j.B) {
     // XX = SI + SQ, XY = SU + i SV, YX = SU - i SV, YY = SI - SQ
-    R* out = coh + (int64_t)k * 8 * plane + (int64_t)tf * B + b;
+    const int64_t plane = j.plane;
+    R* out = reinterpret_cast<R*>(j.coh) + (int64_t)k * 8 * plane + (int64_t)tf * j.B + b;
     out[0 * plane] = iR + qR;
     out[1 * plane] = iI + qI;
     out[2 * plane] = uR - vI;
@@ -118,16 +118,52 @@ __global__ __launch_bounds__(kThreads) void k_predict(
   }
 }
 
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_predict(PredictJob j) {
+  __shared__ PredictShared sh;
+  predict_tile<R>(j, blockIdx.x, blockIdx.y, blockIdx.z, sh);
+}
+
+// Persistent batched predict over several solves: the workgroups walk the flattened list of
+// (job, cluster, timeslot-channel, baseline tile) items with a grid stride.  Each item runs
+// exactly the per-thread arithmetic of k_predict, so a solve predicted in a batch is bitwise
+// identical to the same solve predicted alone.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_predict_batch(const PredictJob* __restrict__ jobs,
+                                                           int njobs, int64_t total) {
+  __shared__ PredictShared sh;
+  for (int64_t vb = blockIdx.x; vb < total; vb += gridDim.x) {
+    int jj = 0;
+    while (jj + 1 < njobs && jobs[jj + 1].first_block <= vb) ++jj;
+    const PredictJob& j = jobs[jj];
+    const int64_t local = vb - j.first_block;
+    const int64_t nbt = (j.B + kThreads - 1) / kThreads;
+    const int TF = j.T * j.F;
+    const int64_t btile = local % nbt;
+    const int64_t rest = local / nbt;
+    predict_tile<R>(j, btile, (int)(rest % TF), (int)(rest / TF), sh);
+    __syncthreads();
+  }
+}
+
 }  // namespace
 
 template <typename R>
 hipError_t launch_predict(const ObsDev& o, int K, const int32_t* offs_dev, const int32_t*,
                           const double* l, const double* m, const double* I, const double* Q,
                           const double* U, const double* V, R* coh, hipStream_t st) {
-  const int64_t plane = (int64_t)o.T * o.F * o.B;
+  PredictJob j = make_predict_job(o, K, offs_dev, l, m, I, Q, U, V, coh);
   dim3 grid((unsigned)((o.B + kThreads - 1) / kThreads), (unsigned)(o.T * o.F), (unsigned)K);
-  hipLaunchKernelGGL(k_predict<R>, grid, dim3(kThreads), 0, st, o.u, o.v, o.w, o.freq, l, m, I, Q,
-                     U, V, offs_dev, o.B, o.F, plane, coh);
+  hipLaunchKernelGGL(k_predict<R>, grid, dim3(kThreads), 0, st, j);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_predict_batch(const PredictJob* jobs_dev, int njobs, int64_t total_blocks,
+                                int grid, hipStream_t st) {
+  if (total_blocks <= 0) return hipSuccess;
+  const int g = (int)std::min<int64_t>(total_blocks, (int64_t)grid);
+  hipLaunchKernelGGL(k_predict_batch<R>, dim3(g), dim3(kThreads), 0, st, jobs_dev, njobs, total_blocks);
   return hipGetLastError();
 }
 
@@ -139,5 +175,7 @@ template hipError_t launch_predict<double>(const ObsDev&, int, const int32_t*, c
                                            const double*, const double*, const double*,
                                            const double*, const double*, const double*, double*,
                                            hipStream_t);
+template hipError_t launch_predict_batch<float>(const PredictJob*, int, int64_t, int, hipStream_t);
+template hipError_t launch_predict_batch<double>(const PredictJob*, int, int64_t, int, hipStream_t);
 
 }  // namespace ddc

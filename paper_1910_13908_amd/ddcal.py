@@ -34,7 +34,9 @@ OK, EINVAL, ENOMEM, EDEVICE, ENOTPD, ENONFINITE, ETIMEOUT = 0, -1, -2, -3, -4, -
 EXPORTS = ("ddc_default_lm_opts", "ddc_create", "ddc_destroy", "ddc_set_stream", "ddc_last_error",
            "ddc_workspace_bytes", "ddc_predict", "ddc_residual", "ddc_add_model",
            "ddc_build_normal_eq", "ddc_damped_solve", "ddc_lm_solve", "ddc_calibrate",
-           "ddc_cost_gradient", "ddc_enable_timing", "ddc_get_timing")
+           "ddc_cost_gradient", "ddc_enable_timing", "ddc_get_timing", "ddc_calibrate_footprint",
+           "ddc_server_create", "ddc_server_destroy", "ddc_server_submit", "ddc_server_wait",
+           "ddc_server_stats", "ddc_server_last_error")
 
 
 class Obs(ct.Structure):
@@ -97,8 +99,20 @@ _lib.ddc_cost_gradient.argtypes = [_vp, ct.POINTER(Obs), ct.c_int32, _vp, _vp, _
 _lib.ddc_enable_timing.argtypes = [_vp, ct.c_int32]
 _lib.ddc_get_timing.argtypes = [_vp, ct.c_int32, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_double),
                                 ct.POINTER(ct.c_double)]
+_lib.ddc_calibrate_footprint.argtypes = [ct.POINTER(Obs), ct.c_int32, ct.c_int32, ct.c_int32]
+_lib.ddc_calibrate_footprint.restype = ct.c_int64
+_lib.ddc_server_create.argtypes = [ct.POINTER(_vp), ct.c_int32, ct.c_int32, ct.c_int64]
+_lib.ddc_server_destroy.argtypes = [_vp]
+_lib.ddc_server_submit.argtypes = [_vp, ct.POINTER(Obs), ct.POINTER(Sky), _vp, _vp, ct.POINTER(CalOpts),
+                                   ct.POINTER(ct.c_int64)]
+_lib.ddc_server_wait.argtypes = [_vp, ct.c_int64, ct.POINTER(LMInfo), ct.POINTER(ct.c_double),
+                                 ct.POINTER(ct.c_double)]
+_lib.ddc_server_stats.argtypes = [_vp, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int64)]
+_lib.ddc_server_last_error.argtypes = [_vp]
+_lib.ddc_server_last_error.restype = ct.c_char_p
 for _f in EXPORTS:
-    if _f not in ("ddc_default_lm_opts", "ddc_last_error", "ddc_workspace_bytes"):
+    if _f not in ("ddc_default_lm_opts", "ddc_last_error", "ddc_workspace_bytes",
+                  "ddc_calibrate_footprint", "ddc_server_last_error"):
         getattr(_lib, _f).restype = ct.c_int
 
 
@@ -244,6 +258,66 @@ class Context:
         work = ct.c_double(0.0)
         self._check(_lib.ddc_get_timing(self.h, which, ct.byref(n), ct.byref(ms), ct.byref(work)))
         return n.value, ms.value, work.value
+
+
+def calibrate_footprint(obs: "DeviceObs", n_clusters: int, n_sweeps: int, precision: int) -> int:
+    return int(_lib.ddc_calibrate_footprint(ct.byref(obs.c), n_clusters, n_sweeps, precision))
+
+
+class Server:
+    """Continuous-batching calibration server (see ddc_server_* in include/ddcal.h).
+
+    ``submit`` keeps references to the request's tensors until ``wait`` returns, so the
+    device memory stays valid while the library uses it.
+    """
+
+    def __init__(self, device: int = 0, n_slots: int = 4, hbm_budget_bytes: int = 16 << 30):
+        h = _vp()
+        st = _lib.ddc_server_create(ct.byref(h), device, n_slots, int(hbm_budget_bytes))
+        if st != OK:
+            raise DdcError(st, "ddc_server_create failed")
+        self.h = h
+        self._keep = {}
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.ddc_server_destroy(self.h)
+            self.h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, obs: "DeviceObs", sky: "DeviceSky", vis, jones, n_sweeps: int, lm: LMOpts) -> int:
+        opts = CalOpts(n_sweeps=n_sweeps, lm=lm)
+        rid = ct.c_int64(0)
+        st = _lib.ddc_server_submit(self.h, ct.byref(obs.c), ct.byref(sky.c), _ptr(vis), _ptr(jones),
+                                    ct.byref(opts), ct.byref(rid))
+        if st != OK:
+            raise DdcError(st, _lib.ddc_server_last_error(self.h).decode())
+        self._keep[rid.value] = (obs, sky, vis, jones, n_sweeps * sky.K)
+        return rid.value
+
+    def wait(self, rid: int):
+        obs, sky, vis, jones, n_info = self._keep[rid]
+        infos = (LMInfo * max(1, n_info))()
+        lat = ct.c_double(0.0)
+        que = ct.c_double(0.0)
+        st = _lib.ddc_server_wait(self.h, rid, infos, ct.byref(lat), ct.byref(que))
+        del self._keep[rid]
+        if st != OK:
+            raise DdcError(st, _lib.ddc_server_last_error(self.h).decode())
+        return list(infos)[:n_info], lat.value, que.value
+
+    def stats(self):
+        n = ct.c_int64(0)
+        m = ct.c_int32(0)
+        p = ct.c_int64(0)
+        _lib.ddc_server_stats(self.h, ct.byref(n), ct.byref(m), ct.byref(p))
+        return {"completed": n.value, "max_running": m.value, "peak_arena_bytes": p.value}
 
 
 # -- marshalling helpers ------------------------------------------------------------------

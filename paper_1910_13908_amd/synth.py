@@ -67,7 +67,7 @@ class ObsConfig:
 
 
 # The paper's station grid and cluster counts set these workloads; the per-config
-# schedules (sweeps x LM iterations) are fixed totals split as documented in the design doc.
+# schedules (sweeps x LM iterations) split the iteration totals of each workload.
 CONFIGS: Dict[str, ObsConfig] = {
     # N=64 (LOFAR-sized), one cluster of 10 sources, plain FP64 LM, 20 iterations.
     "n64_k1": ObsConfig(64, 1, 10, 10, (150e6,), n_sweeps=1, n_lm=20),

@@ -1,0 +1,94 @@
+"""Continuous-batching server: each result is bitwise the same alone and in the mix, equals
+ddc_calibrate, matches the oracle, and admission respects the HBM budget."""
+import numpy as np
+import pytest
+
+from oracle import rime, lm as olm, align
+from paper_1910_13908_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(16, 1, 2), (24, 2, 2), (32, 3, 1), (20, 1, 3), (28, 2, 2), (12, 3, 2)]   # (N, K, T)
+
+
+@pytest.fixture(scope="module")
+def reqs():
+    import torch
+    from paper_1910_13908_amd import ddcal as dd
+    assert torch.cuda.is_available()
+    out = []
+    for i, (N, K, T) in enumerate(SHAPES):
+        cfg = synth.ObsConfig(N, K, 4, T, (150e6,), jones_amp=0.1)
+        ob = synth.make_obs(cfg, seed=100 + i)
+        V, C = rime.make_vis(ob)
+        out.append(dict(ob=ob, V=V, C=C, obs=dd.device_obs(ob), sky=dd.device_sky(ob),
+                        Vd=torch.as_tensor(dd.planes(V), dtype=torch.float32, device="cuda").contiguous(),
+                        J0=torch.as_tensor(dd.jones_real(synth.identity_jones(K, N)), device="cuda").contiguous()))
+    return dd, out
+
+
+SWEEPS, NLM = 2, 8
+
+
+def _serve(dd, reqs, n_slots, budget, order=None):
+    srv = dd.Server(0, n_slots=n_slots, hbm_budget_bytes=budget)
+    lm = dd.default_lm_opts(n_iter=NLM, precision=dd.MIXED)
+    Js = [r["J0"].clone() for r in reqs]
+    order = order or list(range(len(reqs)))
+    ids = {}
+    for i in order:
+        ids[i] = srv.submit(reqs[i]["obs"], reqs[i]["sky"], reqs[i]["Vd"], Js[i], SWEEPS, lm)
+    infos = {i: srv.wait(ids[i])[0] for i in order}
+    st = srv.stats()
+    srv.close()
+    return Js, infos, st
+
+
+def test_alone_equals_mix_bitwise(reqs):
+    import torch
+    dd, rs = reqs
+    alone = []
+    for r in rs:                              # one at a time on a one-slot server
+        Js, infos, _ = _serve(dd, [r], 1, 1 << 30)
+        alone.append((Js[0], infos[0]))
+    Jm, im, st = _serve(dd, rs, 4, 1 << 30, order=[3, 0, 5, 1, 4, 2])
+    assert st["completed"] == len(rs) and st["max_running"] >= 2
+    for i, r in enumerate(rs):
+        assert torch.equal(Jm[i], alone[i][0]), i
+        assert [x.cost for x in im[i]] == [x.cost for x in alone[i][1]]
+    # the server's batched predict path equals the plain ddc_calibrate
+    ctx = dd.Context(0)
+    for i, r in enumerate(rs):
+        J = r["J0"].clone()
+        ctx.calibrate(r["obs"], r["sky"], r["Vd"], J, SWEEPS, dd.default_lm_opts(n_iter=NLM, precision=dd.MIXED))
+        assert torch.equal(J, Jm[i]), i
+    ctx.close()
+
+
+def test_served_results_match_oracle(reqs):
+    dd, rs = reqs
+    Js, infos, _ = _serve(dd, rs, 3, 1 << 30)
+    for i, r in enumerate(rs):
+        ob = r["ob"]
+        Jo, Ro, io, _ = olm.calibrate(r["V"], r["C"], synth.identity_jones(ob.K, ob.N), ob.ant_p, ob.ant_q,
+                                      n_sweeps=SWEEPS, n_lm=NLM)
+        Jg = dd.jones_complex(Js[i].cpu().numpy())
+        for k in range(ob.K):
+            assert align.align_error(Jg[k], Jo[k]) <= 1e-3, (i, k)
+
+
+def test_admission_respects_hbm_budget(reqs):
+    dd, rs = reqs
+    foot = [dd.calibrate_footprint(r["obs"], r["ob"].K, SWEEPS, dd.MIXED) for r in rs]
+    budget = int(max(foot) * 1.2) + (1 << 20)       # room for one solve at a time
+    Js, infos, st = _serve(dd, rs, 4, budget)
+    assert st["completed"] == len(rs)
+    assert st["peak_arena_bytes"] <= budget
+    assert st["max_running"] == 1 or sum(sorted(foot)[:2]) <= budget
+    with pytest.raises(dd.DdcError):
+        srv = dd.Server(0, n_slots=2, hbm_budget_bytes=max(foot) // 2 + (1 << 20))
+        try:
+            srv.submit(rs[2]["obs"], rs[2]["sky"], rs[2]["Vd"], rs[2]["J0"].clone(), SWEEPS,
+                       dd.default_lm_opts(n_iter=NLM, precision=dd.MIXED))
+        finally:
+            srv.close()

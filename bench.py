@@ -36,7 +36,136 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
+    ap.add_argument("--mode", default="lm", choices=["lm", "serve", "lbfgs"],
+                    help="lm: the headline calibration step; serve: the request stream; "
+                         "lbfgs: gradient-based solve vs LM")
+    ap.add_argument("--requests", type=int, default=200)
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--with-serve", action="store_true",
+                    help="also measure the served stream in the lm mode")
     return ap.parse_args()
+
+
+def _percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * q
+    lo, hi = int(np.floor(k)), int(np.ceil(k))
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def serve_measure(n_requests=200, n_slots=4, seed=0, precision="mixed"):
+    """Served stream: closed loop (all at t=0) for the saturation rate, then Poisson arrivals
+    at 0.5x and 0.9x that rate; solves/s and p50/p99 latency from submit to completion."""
+    import threading
+    import queue
+    import torch
+    from paper_1910_13908_amd import synth, ddcal as dd
+    prec = dd.MIXED if precision == "mixed" else dd.FP64
+    dt = torch.float32 if prec == dd.MIXED else torch.float64
+    ctx = dd.Context(0)
+    reqs = []
+    gen = torch.Generator(device="cuda")
+    for cfg, rseed in synth.serving_configs(n_requests, seed):
+        ob = synth.make_obs(cfg, seed=rseed, with_noise=False)
+        obs, sky = dd.device_obs(ob), dd.device_sky(ob)
+        gen.manual_seed(rseed)
+        noise = (cfg.sigma_jy * np.sqrt(0.5)) * torch.randn((8, ob.T, ob.F, ob.B), generator=gen,
+                                                            device="cuda", dtype=torch.float64)
+        noise = noise.to(dt).contiguous()
+        coh = ctx.predict(obs, sky, prec)
+        Jt = torch.as_tensor(dd.jones_real(ob.jones_true), device="cuda").contiguous()
+        V = torch.empty_like(noise)
+        ctx.add_model(obs, ob.K, noise, coh, Jt, 1.0, prec, V)
+        del coh, noise
+        J0 = torch.as_tensor(dd.jones_real(synth.identity_jones(ob.K, ob.N)), device="cuda").contiguous()
+        reqs.append(dict(cfg=cfg, obs=obs, sky=sky, V=V, J0=J0, J=J0.clone(), K=ob.K, N=ob.N))
+    torch.cuda.synchronize()
+    ctx.close()
+    foot = max(dd.calibrate_footprint(r["obs"], r["K"], r["cfg"].n_sweeps, prec) for r in reqs)
+    budget = int(n_slots * foot * 1.05) + (64 << 20)
+    srv = dd.Server(0, n_slots=n_slots, hbm_budget_bytes=budget)
+
+    def run(arrivals):
+        for r in reqs:
+            r["J"].copy_(r["J0"])
+        torch.cuda.synchronize()
+        q = queue.Queue()
+        lat = []
+
+        def collector():
+            while True:
+                item = q.get()
+                if item is None:
+                    return
+                _, l, _ = srv.wait(item)
+                lat.append(l)
+
+        th = threading.Thread(target=collector)
+        th.start()
+        t0 = time.perf_counter()
+        for r, ta in zip(reqs, arrivals):
+            dtw = t0 + ta - time.perf_counter()
+            if dtw > 0:
+                time.sleep(dtw)
+            lm = dd.default_lm_opts(n_iter=r["cfg"].n_lm, precision=prec)
+            q.put(srv.submit(r["obs"], r["sky"], r["V"], r["J"], r["cfg"].n_sweeps, lm))
+        q.put(None)
+        th.join()
+        el = time.perf_counter() - t0
+        return {"solves_per_s": len(reqs) / el, "p50_latency_s": _percentile(lat, 0.5),
+                "p99_latency_s": _percentile(lat, 0.99), "elapsed_s": el}
+
+    run(np.zeros(len(reqs)))                 # warm-up pass (workspaces, code objects)
+    closed = run(np.zeros(len(reqs)))
+    sat = closed["solves_per_s"]
+    out = {"requests": len(reqs), "slots": n_slots, "arena_bytes": budget,
+           "mix": "N in {64,128,256,384,512}, K in {1,5,10,20} x 20 sources, T=10, F=1",
+           "closed_loop": closed}
+    for frac in (0.5, 0.9):
+        arr = synth.poisson_arrivals(frac * sat, len(reqs), seed=seed + 7)
+        out[f"poisson_{frac}x"] = dict(run(arr), rate_hz=frac * sat)
+    out["server"] = srv.stats()
+    srv.close()
+    return out
+
+
+def lbfgs_measure(seed=0, n_iter=200):
+    """Gradient-based solve (adjoint kernel + torch L-BFGS) vs LM on the N=256 workload."""
+    import torch
+    from paper_1910_13908_amd import synth, ddcal as dd, autograd as ag
+    cfg = synth.CONFIGS["n256_k10"]
+    ob = synth.make_obs(cfg, seed=seed)
+    ctx = dd.Context(0)
+    obs, sky = dd.device_obs(ob), dd.device_sky(ob)
+    out = {"workload": "n256_k10: N=256, K=10 x 20 sources, T=10, F=2"}
+    for pname, prec, dt in (("mixed", dd.MIXED, torch.float32), ("fp64", dd.FP64, torch.float64)):
+        noise = torch.as_tensor(dd.planes(ob.noise), dtype=dt, device="cuda").contiguous()
+        coh = ctx.predict(obs, sky, prec)
+        Jt = torch.as_tensor(dd.jones_real(ob.jones_true), device="cuda").contiguous()
+        V = torch.empty_like(noise)
+        ctx.add_model(obs, ob.K, noise, coh, Jt, 1.0, prec, V)
+        J0 = torch.as_tensor(dd.jones_real(synth.identity_jones(ob.K, ob.N)), device="cuda").contiguous()
+        prob = ag.Problem(ctx, obs, ob.K, V, coh, prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Jl, costs = ag.lbfgs_calibrate(prob, J0, n_iter=n_iter)
+        torch.cuda.synchronize()
+        t_l = time.perf_counter() - t0
+        J = J0.clone()
+        t0 = time.perf_counter()
+        infos = ctx.calibrate(obs, sky, V, J, cfg.n_sweeps, dd.default_lm_opts(n_iter=cfg.n_lm, precision=prec))
+        torch.cuda.synchronize()
+        t_m = time.perf_counter() - t0
+        out[pname] = {"lbfgs_final_cost": costs[-1], "lbfgs_s": t_l, "lbfgs_iters": n_iter,
+                      "lm_final_cost": infos[-1][-1].cost, "lm_s": t_m,
+                      "lm_iters": cfg.n_sweeps * ob.K * cfg.n_lm,
+                      "cost_at_truth": ctx.residual(obs, ob.K, V, coh, Jt, prec, None)}
+        del V, coh, noise
+        torch.cuda.empty_cache()
+    ctx.close()
+    return out
 
 
 def cpu_baseline(cfg, seed):
@@ -81,6 +210,17 @@ def main():
         sys.exit(2)
     import torch
     from paper_1910_13908_amd import synth, ddcal as dd
+
+    if args.mode == "serve":
+        res = serve_measure(args.requests, args.slots, args.seed, args.precision)
+        c = res["closed_loop"]
+        print(json.dumps({"metric": "served solves/s", "value": c["solves_per_s"], "unit": "solves/s",
+                          "n_gpus": 1, "higher_is_better": True, "data": "synthetic", "serve": res}),
+              flush=True)
+        return
+    if args.mode == "lbfgs":
+        print(json.dumps({"metric": "L-BFGS vs LM", "lbfgs": lbfgs_measure(args.seed)}), flush=True)
+        return
 
     cfg = synth.CONFIGS[args.config]
     prec = dd.MIXED if args.precision == "mixed" else dd.FP64
@@ -179,6 +319,9 @@ def main():
         ctx.calibrate(obs, sky, V64, J64, cfg.n_sweeps, lm64, want_info=False)
         torch.cuda.synchronize()
         out["fp64_path_lm_iters_per_s"] = n_lm_per_step / (time.perf_counter() - t0)
+
+    if args.with_serve:
+        out["served"] = serve_measure(args.requests, args.slots, args.seed, args.precision)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, args.seed)

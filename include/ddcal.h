@@ -212,7 +212,7 @@ typedef struct ddc_server ddc_server;
 int64_t ddc_calibrate_footprint(const ddc_obs* obs, int32_t n_clusters, int32_t n_sweeps,
                                 int32_t precision);
 /* Server on `device` with n_slots concurrent solves (1..64) and an HBM arena of
- * hbm_budget_bytes allocated up front (DDC_ENOMEM if that fails). */
+ * hbm_budget_bytes (>= 64 KiB) allocated up front (DDC_ENOMEM if that fails). */
 ddc_status ddc_server_create(ddc_server** out, int32_t device, int32_t n_slots,
                              int64_t hbm_budget_bytes);
 /* Finishes every submitted request, then releases everything. */

@@ -106,11 +106,32 @@ __device__ bool wait_flag(const uint32_t* flag, SyncArea* sync, int32_t* status)
       }
       __builtin_amdgcn_s_sleep(2);
     }
-    __atomic_thread_fence(__ATOMIC_ACQUIRE);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     s_ok = ok;
   }
   __syncthreads();
   return s_ok != 0;
+}
+
+// Number of leading K in [0, nK) whose flags (I_a, K) and (I_b, K) are already set, found
+// with one relaxed load per flag in parallel and one agent-scope acquire for the whole
+// prefix, so the common case (operands finished long ago) pays a single fence.
+__device__ int ready_prefix(const uint32_t* flags, int T, int IA, int IB, int nK) {
+  __shared__ int s_first_missing;
+  if (threadIdx.x == 0) s_first_missing = nK;
+  __syncthreads();
+  for (int K = threadIdx.x; K < nK; K += blockDim.x) {
+    const uint32_t ti_a = (uint32_t)(K * T - (K * (K - 1)) / 2 + (IA - K));
+    const uint32_t ti_b = (uint32_t)(K * T - (K * (K - 1)) / 2 + (IB - K));
+    const bool ready = __hip_atomic_load(flags + ti_a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u &&
+                       __hip_atomic_load(flags + ti_b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+    if (!ready) atomicMin(&s_first_missing, K);
+  }
+  __syncthreads();
+  const int n = s_first_missing;
+  if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  __syncthreads();
+  return n;
 }
 
 __device__ __forceinline__ void publish(uint32_t* flag) {
@@ -283,6 +304,9 @@ __device__ __forceinline__ void wave_sync_lds() {
 }
 
 // Wave 0: factor columns 16P..16P+15 (rows >= 16P) in place; returns nonzero on a bad pivot.
+// Lane i keeps its panel row in registers; row c of the panel (needed by every lane for
+// column c) is broadcast from lane c with readlane, so the serial column loop never goes
+// through LDS.  The finished panel is written back once at the end.
 template <typename R, int P>
 __device__ int panel_factor(R* A, R* rdiag) {
   constexpr int STR = Mfma<R>::STR;
@@ -292,15 +316,15 @@ __device__ int panel_factor(R* A, R* rdiag) {
 #pragma unroll
   for (int j = 0; j < 16; ++j) a[j] = A[i * STR + c0 + j];
   int bad = 0;
+  R rd = (R)0;
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
     const int c = c0 + j;
-    const R* rowc = A + c * STR + c0;
     R d0 = 0, d1 = 0;
 #pragma unroll
     for (int k = 0; k < j; k += 2) {
-      d0 = fma(a[k], rowc[k], d0);
-      if (k + 1 < j) d1 = fma(a[k + 1], rowc[k + 1], d1);
+      d0 = fma(a[k], bcast_lane(a[k], c), d0);
+      if (k + 1 < j) d1 = fma(a[k + 1], bcast_lane(a[k + 1], c), d1);
     }
     const R x = a[j] - (d0 + d1);
     R d = bcast_lane(x, c);
@@ -309,12 +333,14 @@ __device__ int panel_factor(R* A, R* rdiag) {
       d = (R)1;
     }
     const R r = rsq_full(d);
-    const R lic = (i == c) ? d * r : x * r;
-    a[j] = lic;
-    if (i >= c) A[i * STR + c] = lic;
-    if (i == c) rdiag[c] = r;
-    wave_sync_lds();
+    a[j] = (i == c) ? d * r : x * r;
+    if (i == c) rd = r;
   }
+  // rows above the panel keep their (upper-triangle) values; rows at or below write L
+#pragma unroll
+  for (int j = 0; j < 16; ++j)
+    if (i >= c0 + j) A[i * STR + c0 + j] = a[j];
+  if (i >= c0 && i < c0 + 16) rdiag[i] = rd;
   return bad;
 }
 
@@ -529,8 +555,13 @@ __device__ __forceinline__ bool accumulate(typename Mfma<R>::acc_t (&acc1)[2][2]
   constexpr int TILE = 64 * STR;
   if (nK <= 0) return true;
   TileRegs<R> ra, rb;
-  bool ok = wait_flag(flags + tile_index(IA, 0, T), sync, status);
-  if (ok && IB != IA) ok = wait_flag(flags + tile_index(IB, 0, T), sync, status);
+  // flags of the first `ready` K are known set (and acquired); wait on the rest one by one
+  const int ready = ready_prefix(flags, T, IA, IB, nK);
+  bool ok = true;
+  if (ready < 1) {
+    ok = wait_flag(flags + tile_index(IA, 0, T), sync, status);
+    if (ok && IB != IA) ok = wait_flag(flags + tile_index(IB, 0, T), sync, status);
+  }
   tile_fetch<R>(Lt + (int64_t)tile_index(IA, 0, T) * 4096, ra);
   tile_fetch<R>(Lt + (int64_t)tile_index(IB, 0, T) * 4096, rb);
   tile_stash<R>(ra, lds);
@@ -540,8 +571,10 @@ __device__ __forceinline__ bool accumulate(typename Mfma<R>::acc_t (&acc1)[2][2]
   for (int K = 0; K < nK; ++K) {
     const bool more = K + 1 < nK;
     if (more && ok) {
-      ok = wait_flag(flags + tile_index(IA, K + 1, T), sync, status);
-      if (ok && IB != IA) ok = wait_flag(flags + tile_index(IB, K + 1, T), sync, status);
+      if (K + 1 >= ready) {
+        ok = wait_flag(flags + tile_index(IA, K + 1, T), sync, status);
+        if (ok && IB != IA) ok = wait_flag(flags + tile_index(IB, K + 1, T), sync, status);
+      }
       tile_fetch<R>(Lt + (int64_t)tile_index(IA, K + 1, T) * 4096, ra);
       tile_fetch<R>(Lt + (int64_t)tile_index(IB, K + 1, T) * 4096, rb);
     }
@@ -631,11 +664,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
       __syncthreads();
       const int bad = cholinv_tile<R>(lds, lds + TILE, rdiag);
       if (bad && tid == 0 && status) atomicOr(status, 1);
-      R* dstL = Lt + (int64_t)tile_index(s, s, T) * 4096;
+      // only the inverse of a diagonal tile is consumed (by the products and the solves)
       R* dstX = Linv + (int64_t)s * 4096;
       for (int e = tid; e < 4096; e += kThreads) {
         const int r = e >> 6, c = e & 63;
-        dstL[e] = (c <= r) ? lds[r * STR + c] : (R)0;
         dstX[e] = lds[TILE + r * STR + c];
       }
       publish(flags + tile_index(s, s, T));

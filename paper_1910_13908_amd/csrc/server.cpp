@@ -372,7 +372,7 @@ int64_t ddc_calibrate_footprint(const ddc_obs* obs, int32_t n_clusters, int32_t 
 
 ddc_status ddc_server_create(ddc_server** out, int32_t device, int32_t n_slots,
                              int64_t hbm_budget_bytes) {
-  if (!out || n_slots < 1 || n_slots > 64 || hbm_budget_bytes < (1 << 20)) return DDC_EINVAL;
+  if (!out || n_slots < 1 || n_slots > 64 || hbm_budget_bytes < (64 << 10)) return DDC_EINVAL;
   *out = nullptr;
   ddc_server* s = new ddc_server();
   s->device = device;

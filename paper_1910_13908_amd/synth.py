@@ -225,6 +225,24 @@ def make_obs(cfg: ObsConfig, seed: int = 0, with_noise: bool = True) -> Obs:
                jones_true=np.ascontiguousarray(J), noise=noise)
 
 
+SERVE_N = (64, 128, 256, 384, 512)
+SERVE_K = (1, 5, 10, 20)
+
+
+def serving_configs(n_requests: int = 200, seed: int = 0):
+    """Request mix of the serving workload: N uniform over the paper's station counts, K uniform
+    over {1, 5, 10, 20} clusters of 20 sources, T=10, F=1, 3 km disk, J = I + 0.1 CN(0,1).
+    Schedules: K = 1 runs 1 sweep x 20 LM iterations, otherwise 2 sweeps x 10."""
+    rng = np.random.default_rng(np.random.SeedSequence(seed).spawn(5)[4])
+    out = []
+    for i in range(n_requests):
+        N = int(rng.choice(SERVE_N))
+        K = int(rng.choice(SERVE_K))
+        sweeps, n_lm = (1, 20) if K == 1 else (2, 10)
+        out.append((ObsConfig(N, K, 20, 10, (150e6,), n_sweeps=sweeps, n_lm=n_lm), 1000 + i))
+    return out
+
+
 def identity_jones(n_clusters: int, n_stations: int) -> np.ndarray:
     return np.ascontiguousarray(np.broadcast_to(np.eye(2, dtype=np.complex128),
                                                 (n_clusters, n_stations, 2, 2)))

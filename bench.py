@@ -36,9 +36,11 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
-    ap.add_argument("--mode", default="lm", choices=["lm", "serve", "lbfgs"],
+    ap.add_argument("--mode", default="lm", choices=["lm", "serve", "lbfgs", "copy", "scan"],
                     help="lm: the headline calibration step; serve: the request stream; "
-                         "lbfgs: gradient-based solve vs LM")
+                         "lbfgs: gradient-based solve vs LM; copy: a plain device copy of "
+                         "known size (reference for the HBM byte counters); scan: calibration "
+                         "runtime over the station-count x cluster-count grid")
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--with-serve", action="store_true",
@@ -168,6 +170,91 @@ def lbfgs_measure(seed=0, n_iter=200):
     return out
 
 
+def scan_measure(seed=0, n_lm=10, oracle_max_n=128):
+    """Calibration runtime over the paper's station grid and cluster counts (its runtime-vs-N
+    and runtime-vs-K experiments, Section 3): N in {64, 128, 256, 384, 512} x K in
+    {1, 5, 10, 20, 50} clusters of 20 sources, T=10, F=1, one SAGE sweep of n_lm LM iterations
+    per cluster, mixed and FP64.  The time covers predict + calibrate with data resident in
+    HBM.  The CPU line is the FP64 oracle's time for one LM iteration of one cluster, for
+    N <= oracle_max_n (larger N take minutes per iteration on the host)."""
+    import torch
+    from paper_1910_13908_amd import synth, ddcal as dd
+    ctx = dd.Context(0)
+    rows = []
+    for N in synth.SERVE_N:
+        for K in (1, 5, 10, 20, 50):
+            cfg = synth.ObsConfig(N, K, 20, 10, (150e6,), n_sweeps=1, n_lm=n_lm)
+            ob = synth.make_obs(cfg, seed=seed)
+            obs, sky = dd.device_obs(ob), dd.device_sky(ob)
+            row = {"N": N, "K": K, "vis": ob.B * ob.T * ob.F}
+            for pname, prec, dt in (("mixed", dd.MIXED, torch.float32), ("fp64", dd.FP64, torch.float64)):
+                noise = torch.as_tensor(dd.planes(ob.noise), dtype=dt, device="cuda").contiguous()
+                coh = ctx.predict(obs, sky, prec)
+                Jt = torch.as_tensor(dd.jones_real(ob.jones_true), device="cuda").contiguous()
+                V = torch.empty_like(noise)
+                ctx.add_model(obs, K, noise, coh, Jt, 1.0, prec, V)
+                del coh, noise
+                J0 = torch.as_tensor(dd.jones_real(synth.identity_jones(K, N)), device="cuda").contiguous()
+                J = J0.clone()
+                lm = dd.default_lm_opts(n_iter=n_lm, precision=prec)
+                ctx.calibrate(obs, sky, V, J, 1, lm, want_info=False)     # warm-up
+                torch.cuda.synchronize()
+                reps = 3 if N * K <= 2560 else 1
+                ts = []
+                for _ in range(reps):
+                    J.copy_(J0)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    ctx.calibrate(obs, sky, V, J, 1, lm, want_info=False)
+                    torch.cuda.synchronize()
+                    ts.append(time.perf_counter() - t0)
+                row[f"{pname}_s"] = float(np.median(ts))
+                row[f"{pname}_lm_iters_per_s"] = K * n_lm / row[f"{pname}_s"]
+                del V, J, J0
+                torch.cuda.empty_cache()
+            if K == 1 and N <= oracle_max_n:
+                row["oracle_lm_iter_s"] = _oracle_lm_iteration_s(ob)
+            rows.append(row)
+            print(json.dumps({"scan_row": row}), file=sys.stderr, flush=True)
+    ctx.close()
+    return rows
+
+
+def _oracle_lm_iteration_s(ob):
+    """Host time of one FP64 oracle LM iteration of cluster 0 (normal equations, damped solve,
+    trial cost)."""
+    from oracle import rime, normal_eq as ne, lm as olm
+    from paper_1910_13908_amd import synth
+    offs = ob.cluster_offset[:2]
+    C0 = rime.predict(ob.u, ob.v, ob.w, ob.freqs, ob.l, ob.m, ob.I, ob.Q, ob.U, ob.V, offs)[0]
+    Y = rime.model_cluster(C0, ob.jones_true[0], ob.ant_p, ob.ant_q) + ob.noise
+    J = synth.identity_jones(1, ob.N)[0]
+    t0 = time.perf_counter()
+    H, g, f = ne.normal_equations(Y, C0, J, ob.ant_p, ob.ant_q)
+    mu = max(1e-3, 1e-6) * float(np.max(np.diag(H)))
+    d = olm.damped_solve(H, g, mu)
+    rime.cost(Y - rime.model_cluster(C0, ne.unpack_jones(ne.pack_jones(J) + d), ob.ant_p, ob.ant_q))
+    return time.perf_counter() - t0
+
+
+def copy_measure(mib=1024, reps=5):
+    """A plain device-to-device copy of `mib` MiB, `reps` times: the known-size reference that
+    scales FETCH_SIZE / WRITE_SIZE counter readings into bytes."""
+    import torch
+    n = (mib << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    return {"bytes_read_per_copy": n * 4, "bytes_written_per_copy": n * 4, "copies": reps + 1,
+            "gbs": 2 * n * 4 * reps / el / 1e9}
+
+
 def cpu_baseline(cfg, seed):
     """The FP64 oracle on the host: one LM iteration of cluster 0 at full size."""
     from oracle import rime, normal_eq as ne, lm as olm
@@ -217,6 +304,13 @@ def main():
         print(json.dumps({"metric": "served solves/s", "value": c["solves_per_s"], "unit": "solves/s",
                           "n_gpus": 1, "higher_is_better": True, "data": "synthetic", "serve": res}),
               flush=True)
+        return
+    if args.mode == "scan":
+        print(json.dumps({"metric": "calibration runtime scan", "data": "synthetic",
+                          "scan": scan_measure(args.seed)}), flush=True)
+        return
+    if args.mode == "copy":
+        print(json.dumps({"metric": "device copy", "copy": copy_measure()}), flush=True)
         return
     if args.mode == "lbfgs":
         print(json.dumps({"metric": "L-BFGS vs LM", "lbfgs": lbfgs_measure(args.seed)}), flush=True)

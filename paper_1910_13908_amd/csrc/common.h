@@ -127,15 +127,19 @@ hipError_t launch_cost_adjoint(const ObsDev& o, int K, const R* res, const R* co
 
 // k_chol.hip
 // Factor H + mu I (mu from mu_dev if non-null); with g != null also y = L^{-1} g.
+// part: scratch of [T][2][4096] elements for the diagonal partial sums; flags: T(T+1)/2 + T.
 template <typename R>
 hipError_t launch_cholesky(const R* Hc, int ld, int n_pad, const double* mu_dev, double mu_host,
-                           const double* g, double* y, R* Lt, R* Linv, SyncArea* sync,
+                           const double* g, double* y, R* Lt, R* Linv, R* part, SyncArea* sync,
                            uint32_t* flags, uint32_t* yflags, int32_t* status, hipStream_t st,
                            int n_wg);
+// x = L^{-1} b (forward) or L^{-T} b (backward); acc_out (nullable) += x; part_sum: n_pad
+// doubles of scratch; flags: 2 T entries.
 template <typename R>
 hipError_t launch_trsv(bool forward, const R* Lt, const R* Linv, int n_pad, const double* b,
-                       double* x, double* acc_out, SyncArea* sync, uint32_t* flags,
-                       int32_t* status, const LMState* lm, int gate, hipStream_t st);
+                       double* x, double* acc_out, double* part_sum, SyncArea* sync,
+                       uint32_t* flags, int32_t* status, const LMState* lm, int gate,
+                       hipStream_t st);
 // s = g - (H + mu I) d (FP64) via per-tile partials prow/pcol ([T(T+1)/2][64] each).
 template <typename R>
 hipError_t launch_refine_resid(const R* Hc, int ld, int n_pad, const double* mu_dev,

@@ -59,8 +59,8 @@ struct ddc_ctx {
   LMState* lm() { return reinterpret_cast<LMState*>(sync); }
   SyncArea* area(int i) { return reinterpret_cast<SyncArea*>(sync + 512 + 64 * i); }
   uint32_t* chol_flags() { return reinterpret_cast<uint32_t*>(sync + 1024); }
-  uint32_t* fwd_flags() { return chol_flags() + kMaxTiles * (kMaxTiles + 1) / 2; }
-  uint32_t* bwd_flags() { return fwd_flags() + kMaxTiles; }
+  uint32_t* fwd_flags() { return chol_flags() + kMaxTiles * (kMaxTiles + 1) / 2 + kMaxTiles; }
+  uint32_t* bwd_flags() { return fwd_flags() + 2 * kMaxTiles; }
 };
 
 namespace {
@@ -219,8 +219,8 @@ ddc_status obs_dev(ddc_ctx* c, const ddc_obs* o, ObsDev& d) {
 // Buffers of one damped solve / LM solve in the workspace.
 struct SolveBufs {
   int n, n_pad, T, ld;
-  void *Hc, *Lt, *Linv, *part;
-  double *g, *diag, *d, *y, *s, *e, *cost_part, *s_part, *scalar, *prow, *pcol;
+  void *Hc, *Lt, *Linv, *part, *cpart;
+  double *g, *diag, *d, *y, *s, *e, *cost_part, *s_part, *scalar, *prow, *pcol, *tpart;
   size_t h_off;
 };
 
@@ -243,6 +243,8 @@ void layout_solve(Bump& bp, SolveBufs& b, int n, size_t es, int64_t B, int64_t n
   const size_t ntiles = (size_t)b.T * (b.T + 1) / 2;
   offs.push_back(bp.take(ntiles * 64 * sizeof(double)));               // prow
   offs.push_back(bp.take(ntiles * 64 * sizeof(double)));               // pcol
+  offs.push_back(bp.take((size_t)b.T * 2 * 4096 * es));                 // Cholesky partial sums
+  offs.push_back(bp.take(np * sizeof(double)));                         // solve partial sums
 }
 
 void bind_solve(ddc_ctx* c, SolveBufs& b, const std::vector<size_t>& o) {
@@ -262,6 +264,8 @@ void bind_solve(ddc_ctx* c, SolveBufs& b, const std::vector<size_t>& o) {
   b.scalar = reinterpret_cast<double*>(w + o[12]);
   b.prow = reinterpret_cast<double*>(w + o[13]);
   b.pcol = reinterpret_cast<double*>(w + o[14]);
+  b.cpart = w + o[15];
+  b.tpart = reinterpret_cast<double*>(w + o[16]);
   b.h_off = o[0];
 }
 
@@ -290,13 +294,14 @@ ddc_status enqueue_solve(ddc_ctx* c, SolveBufs& b, LMState* lm, int refine_max, 
   R* Li = reinterpret_cast<R*>(b.Linv);
   // the factorisation also runs the forward substitution y = L^{-1} g
   DDCCK(timed(c, T_CHOL, chol_flop(b.n), [&] {
-    return launch_cholesky<R>(Hc, b.ld, b.n_pad, &lm->mu_eff, 0.0, b.g, b.y, Lt, Li, c->area(0),
-                              c->chol_flags(), c->fwd_flags(), &lm->notpd, st, c->chol_wg);
+    return launch_cholesky<R>(Hc, b.ld, b.n_pad, &lm->mu_eff, 0.0, b.g, b.y, Lt, Li,
+                              reinterpret_cast<R*>(b.cpart), c->area(0), c->chol_flags(),
+                              c->fwd_flags(), &lm->notpd, st, c->chol_wg);
   }));
   const double tri_bytes = (double)b.n_pad * (b.n_pad + 64) / 2 * sizeof(R);
   DDCCK(timed(c, T_TRSV, tri_bytes, [&] {
-    return launch_trsv<R>(false, Lt, Li, b.n_pad, b.y, b.d, nullptr, c->area(2), c->bwd_flags(),
-                          &lm->timeout, lm, 1, st);
+    return launch_trsv<R>(false, Lt, Li, b.n_pad, b.y, b.d, nullptr, b.tpart, c->area(2),
+                          c->bwd_flags(), &lm->timeout, lm, 1, st);
   }));
   for (int r = 0; r < refine_max; ++r) {
     DDCCK(timed(c, T_REFINE, (double)b.n_pad * b.n_pad * sizeof(R), [&] {
@@ -305,12 +310,12 @@ ddc_status enqueue_solve(ddc_ctx* c, SolveBufs& b, LMState* lm, int refine_max, 
     }));
     HIPCK(launch_refine_ctrl(lm, b.s_part, b.T, tol * tol, st));
     DDCCK(timed(c, T_TRSV, tri_bytes, [&] {
-      return launch_trsv<R>(true, Lt, Li, b.n_pad, b.s, b.y, nullptr, c->area(1), c->fwd_flags(),
-                            &lm->timeout, lm, 2, st);
+      return launch_trsv<R>(true, Lt, Li, b.n_pad, b.s, b.y, nullptr, b.tpart, c->area(1),
+                            c->fwd_flags(), &lm->timeout, lm, 2, st);
     }));
     DDCCK(timed(c, T_TRSV, tri_bytes, [&] {
-      return launch_trsv<R>(false, Lt, Li, b.n_pad, b.y, b.e, b.d, c->area(2), c->bwd_flags(),
-                            &lm->timeout, lm, 2, st);
+      return launch_trsv<R>(false, Lt, Li, b.n_pad, b.y, b.e, b.d, b.tpart, c->area(2),
+                            c->bwd_flags(), &lm->timeout, lm, 2, st);
     }));
   }
   return DDC_OK;

@@ -9,11 +9,12 @@
 //   I == J:  L_JJ = chol(A_JJ) and X_JJ = L_JJ^{-1}       (blocked 16-column panels + MFMA)
 //   I >  J:  L_IJ = A_IJ X_JJ^T                           (MFMA with the stored inverse)
 //
-// The task that factors diagonal tile s first computes the subdiagonal tile (s, s-1)
-// itself, so the chain of dependent diagonal factorisations has one inter-workgroup hand-off
-// per 64 columns.  With a right-hand side g the same kernel also runs the forward
-// substitution y = L^{-1} g block by block as the factor appears.  A tile publishes a ready
-// flag when it is final; a consumer waits only on flags of tasks with a smaller ticket.  Tickets are claimed only by running workgroups, so the smallest
+// One workgroup walks the diagonal (subdiagonal tile, update, factor and inverse of every
+// diagonal tile in turn) with its operands in LDS, so the dependent chain along the
+// diagonal never waits on another workgroup; the others pre-accumulate what it needs and
+// fill in the rest of the factor.  With a right-hand side g the same kernel also runs the
+// forward substitution y = L^{-1} g block by block as the factor appears.  Results publish
+// ready flags; every wait is on work that is finished or held by a running workgroup.  Tickets are claimed only by running workgroups, so the smallest
 // unfinished ticket never waits on unfinished work and the schedule cannot deadlock without
 // any co-residency guarantee.  Every wait is bounded; on expiry the kernel raises an abort
 // flag, every other wait returns at once, and the status word reports DDC_ETIMEOUT.  The
@@ -514,33 +515,46 @@ __device__ __forceinline__ void acc_load_h(typename Mfma<R>::acc_t (&acc)[2][2],
       }
 }
 
-// Task kinds of the factorisation, in ticket order per step s:
-//   D_s: tile (s, s-1) (s >= 1) and the diagonal tile (s, s) with its inverse;
-//   Y_s: forward-substitution block y_s = X_ss (g_s - sum_{K<s} L_sK y_K);
-//   R_{s-1}: tiles (I, s-1), I >= s+1 (regular tiles of column s-1).
-// Every task depends only on tasks earlier in this order.
-enum { TASK_D = 0, TASK_Y = 1, TASK_R = 2, TASK_NONE = 3 };
+// Roles of the factorisation.  Ticket 0 makes its workgroup the diagonal worker (DW): it
+// factors the diagonal tiles in order, s = 0..T-1, and keeps each inverse in LDS for the next
+// step, so the chain of dependent diagonal factorisations has no inter-workgroup hand-off.
+// At step s it computes the subdiagonal tile L_{s,s-1} = A_{s,s-1} X_{s-1}^T, applies its
+// rank-64 update to the diagonal tile and factors/inverts it.  Every other workgroup takes
+// tickets >= 1 in groups g = 0..T-1:
+//   DA_{g+1} (2 <= g+1 <= T-1): the partial sums -sum_{K <= g-1} L_{g+1,K} L_{g,K}^T and
+//            -sum_{K <= g-1} L_{g+1,K} L_{g+1,K}^T that the DW adds at step g+1;
+//   Y_g:     forward-substitution block y_g = X_gg (g_g - sum_{K<g} L_gK y_K);
+//   R_g:     tiles (I, g), I >= g+2: A_Ig - sum_K L_IK L_gK^T, then times X_gg^T.
+// A task waits only on tasks of earlier groups or on DW steps whose own inputs come from
+// earlier groups, so the schedule cannot deadlock with any number (>= 2) of resident
+// workgroups.
+enum { TASK_DW = 0, TASK_DA = 1, TASK_Y = 2, TASK_R = 3, TASK_NONE = 4 };
 
 __device__ __forceinline__ void decode_task(uint32_t t, int T, int& kind, int& I, int& J) {
   kind = TASK_NONE;
   I = J = 0;
-  if (t == 0) { kind = TASK_D; return; }
-  if (t == 1) { kind = TASK_Y; return; }
-  t -= 2;
-  for (int s = 1; s < T; ++s) {
-    const uint32_t nr = (uint32_t)max(0, T - s - 1);
-    if (t < 2 + nr) {
-      if (t == 0) { kind = TASK_D; I = J = s; }
-      else if (t == 1) { kind = TASK_Y; I = J = s; }
-      else { kind = TASK_R; J = s - 1; I = s + 1 + (int)(t - 2); }
+  if (t == 0) { kind = TASK_DW; return; }
+  t -= 1;
+  for (int g = 0; g < T; ++g) {
+    const uint32_t da = (g >= 1 && g + 1 <= T - 1) ? 1u : 0u;
+    const uint32_t nr = (uint32_t)max(0, T - g - 2);
+    if (t < da + 1 + nr) {
+      if (da) {
+        if (t == 0) { kind = TASK_DA; I = J = g + 1; return; }
+        t -= 1;
+      }
+      if (t == 0) { kind = TASK_Y; I = J = g; return; }
+      kind = TASK_R; J = g; I = g + 2 + (int)(t - 1);
       return;
     }
-    t -= 2 + nr;
+    t -= da + 1 + nr;
   }
 }
 
 __host__ __device__ inline uint32_t chol_tasks(int T) {
-  return (uint32_t)(2 * T + (T >= 2 ? (T - 2) * (T - 1) / 2 : 0));
+  const int da = T >= 2 ? T - 2 : 0;
+  const int nr = T >= 2 ? (T - 2) * (T - 1) / 2 : 0;
+  return (uint32_t)(1 + T + da + nr);
 }
 
 // Accumulate acc1 -= A_K B_K^T (and acc2 -= A_K A_K^T when TWO) over K < nK, where
@@ -596,19 +610,24 @@ template <typename R>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_cholesky(
     const R* __restrict__ Hc, int64_t ld, int T, const double* __restrict__ mu_dev, double mu_host,
     const double* __restrict__ gvec, double* __restrict__ yvec, R* __restrict__ Lt,
-    R* __restrict__ Linv, SyncArea* sync, uint32_t* flags, uint32_t* yflags, int32_t* status) {
+    R* __restrict__ Linv, R* __restrict__ part, SyncArea* sync, uint32_t* flags,
+    uint32_t* yflags, int32_t* status) {
   constexpr int STR = Mfma<R>::STR;
   constexpr int TILE = 64 * STR;
   using acc_t = typename Mfma<R>::acc_t;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  R* lds = reinterpret_cast<R*>(smem_raw);            // 4 tiles: two double-buffered pairs
+  R* lds = reinterpret_cast<R*>(smem_raw);            // 4 tiles
   __shared__ R rdiag[64];
   __shared__ double s_vec[64];
   __shared__ double s_red[kThreads];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x, wv = tid >> 6;
   const int qr = wv >> 1, qc = wv & 1;
   const double mu = mu_dev ? *mu_dev : mu_host;
   const uint32_t ntasks = chol_tasks(T);
+  const uint32_t ntile_flags = (uint32_t)(T * (T + 1) / 2);
+  uint32_t* daflags = flags + ntile_flags;
+  // raw per-thread layout of one accumulator tile: thread tid owns 16 values
+  auto part_ptr = [&](int s, int which) { return part + ((int64_t)s * 2 + which) * 4096 + tid * 16; };
 
   for (;;) {
     const uint32_t t = claim(sync);
@@ -617,7 +636,80 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
     decode_task(t, T, kind, I, J);
     bool ok = true;
 
-    if (kind == TASK_R) {
+    if (kind == TASK_DW) {
+      R* Abuf = lds;
+      R* Xprev = lds + TILE;
+      R* Xcur = lds + 2 * TILE;
+      R* Lbuf = lds + 3 * TILE;
+      for (int st = 0; st < T; ++st) {
+        acc_t accd[2][2];
+        acc_load_h<R>(accd, Hc, ld, st, st, mu, qr, qc);
+        if (st >= 1) {
+          acc_t accs[2][2];
+          acc_load_h<R>(accs, Hc, ld, st, st - 1, 0.0, qr, qc);
+          if (st >= 2) {
+            if (ok) ok = wait_flag(daflags + st, sync, status);
+            const R* ps = part_ptr(st, 0);
+            const R* pd = part_ptr(st, 1);
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+              for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                  accs[bi][bj][v] += ps[(bi * 2 + bj) * 4 + v];
+                  accd[bi][bj][v] += pd[(bi * 2 + bj) * 4 + v];
+                }
+          }
+          acc_to_lds<R>(accs, Abuf, qr, qc);
+          __syncthreads();
+          acc_t ls[2][2];
+#pragma unroll
+          for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj) ls[bi][bj] = acc_t{0, 0, 0, 0};
+          tile_mma<R, false>(ls, Abuf, Xprev, qr, qc);      // L_{s,s-1} = A X_{s-1}^T
+          acc_to_global<R>(ls, Lt + (int64_t)tile_index(st, st - 1, T) * 4096, qr, qc);
+          acc_to_lds<R>(ls, Lbuf, qr, qc);
+          publish(flags + tile_index(st, st - 1, T));
+          __syncthreads();
+          tile_mma<R, true>(accd, Lbuf, Lbuf, qr, qc);
+          __syncthreads();
+        }
+        acc_to_lds<R>(accd, Abuf, qr, qc);
+        __syncthreads();
+        const int bad = cholinv_tile<R>(Abuf, Xcur, rdiag);
+        if (bad && tid == 0 && status) atomicOr(status, 1);
+        R* dstX = Linv + (int64_t)st * 4096;
+        for (int e = tid; e < 4096; e += kThreads) dstX[e] = Xcur[(e >> 6) * STR + (e & 63)];
+        publish(flags + tile_index(st, st, T));
+        __syncthreads();
+        R* tmp = Xprev;
+        Xprev = Xcur;
+        Xcur = tmp;
+      }
+    } else if (kind == TASK_DA) {
+      const int s = I;
+      acc_t accs[2][2], accd[2][2];
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) accs[bi][bj] = accd[bi][bj] = acc_t{0, 0, 0, 0};
+      ok = accumulate<R, true>(accs, accd, Lt, T, s, s - 1, s - 1, lds, sync, flags, status, qr, qc);
+      R* ps = part_ptr(s, 0);
+      R* pd = part_ptr(s, 1);
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            ps[(bi * 2 + bj) * 4 + v] = accs[bi][bj][v];
+            pd[(bi * 2 + bj) * 4 + v] = accd[bi][bj][v];
+          }
+      publish(daflags + s);
+      __syncthreads();
+    } else if (kind == TASK_R) {
       acc_t acc[2][2], dummy[2][2];
       acc_load_h<R>(acc, Hc, ld, I, J, 0.0, qr, qc);
       ok = accumulate<R, false>(acc, dummy, Lt, T, I, J, J, lds, sync, flags, status, qr, qc);
@@ -634,53 +726,15 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
       acc_to_global<R>(out, Lt + (int64_t)tile_index(I, J, T) * 4096, qr, qc);
       publish(flags + tile_index(I, J, T));
       __syncthreads();
-    } else if (kind == TASK_D) {
-      const int s = J;
-      acc_t accd[2][2];
-      acc_load_h<R>(accd, Hc, ld, s, s, mu, qr, qc);
-      if (s >= 1) {
-        acc_t accs[2][2];
-        acc_load_h<R>(accs, Hc, ld, s, s - 1, 0.0, qr, qc);
-        ok = accumulate<R, true>(accs, accd, Lt, T, s, s - 1, s - 1, lds, sync, flags, status, qr, qc);
-        if (ok) ok = wait_flag(flags + tile_index(s - 1, s - 1, T), sync, status);
-        acc_to_lds<R>(accs, lds, qr, qc);
-        tile_to_lds<R>(Linv + (int64_t)(s - 1) * 4096, lds + TILE);
-        __syncthreads();
-        acc_t ls[2][2];
-#pragma unroll
-        for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-          for (int bj = 0; bj < 2; ++bj) ls[bi][bj] = acc_t{0, 0, 0, 0};
-        tile_mma<R, false>(ls, lds, lds + TILE, qr, qc);
-        acc_to_global<R>(ls, Lt + (int64_t)tile_index(s, s - 1, T) * 4096, qr, qc);
-        __syncthreads();
-        acc_to_lds<R>(ls, lds + 2 * TILE, qr, qc);
-        publish(flags + tile_index(s, s - 1, T));
-        __syncthreads();
-        tile_mma<R, true>(accd, lds + 2 * TILE, lds + 2 * TILE, qr, qc);
-        __syncthreads();
-      }
-      acc_to_lds<R>(accd, lds, qr, qc);
-      __syncthreads();
-      const int bad = cholinv_tile<R>(lds, lds + TILE, rdiag);
-      if (bad && tid == 0 && status) atomicOr(status, 1);
-      // only the inverse of a diagonal tile is consumed (by the products and the solves)
-      R* dstX = Linv + (int64_t)s * 4096;
-      for (int e = tid; e < 4096; e += kThreads) {
-        const int r = e >> 6, c = e & 63;
-        dstX[e] = lds[TILE + r * STR + c];
-      }
-      publish(flags + tile_index(s, s, T));
-      __syncthreads();
     } else if (kind == TASK_Y && gvec) {
       // y_J = X_JJ (g_J - sum_{K<J} L_JK y_K), FP64 accumulation
-      const int r = tid & 63, part = tid >> 6;
+      const int r = tid & 63, pt = tid >> 6;
       double acc = 0.0;
       for (int K = 0; K < J && ok; ++K) {
         ok = wait_flag(flags + tile_index(J, K, T), sync, status);
         if (ok) ok = wait_flag(yflags + K, sync, status);
-        const R* tile = Lt + (int64_t)tile_index(J, K, T) * 4096 + r * 64 + part * 16;
-        const double* yv = yvec + 64 * K + part * 16;
+        const R* tile = Lt + (int64_t)tile_index(J, K, T) * 4096 + r * 64 + pt * 16;
+        const double* yv = yvec + 64 * K + pt * 16;
 #pragma unroll
         for (int c = 0; c < 16; ++c) acc = fma((double)tile[c], yv[c], acc);
       }
@@ -689,10 +743,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
       if (tid < 64)
         s_vec[tid] = gvec[64 * J + tid] - (((s_red[tid] + s_red[tid + 64]) + s_red[tid + 128]) + s_red[tid + 192]);
       if (ok) ok = wait_flag(flags + tile_index(J, J, T), sync, status);
-      const R* inv = Linv + (int64_t)J * 4096 + r * 64 + part * 16;
+      const R* inv = Linv + (int64_t)J * 4096 + r * 64 + pt * 16;
       double y = 0.0;
 #pragma unroll
-      for (int c = 0; c < 16; ++c) y = fma((double)inv[c], s_vec[part * 16 + c], y);
+      for (int c = 0; c < 16; ++c) y = fma((double)inv[c], s_vec[pt * 16 + c], y);
       s_red[tid] = y;
       __syncthreads();
       if (tid < 64)
@@ -701,7 +755,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
       __syncthreads();
     }
   }
-  exit_and_reset(sync, flags, (int)(T * (T + 1) / 2), yflags, yflags ? T : 0);
+  exit_and_reset(sync, flags, (int)(ntile_flags + (uint32_t)T), yflags, yflags ? T : 0);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -728,121 +782,132 @@ __device__ __forceinline__ double reduce4(double v, double* sh) {
   return r;
 }
 
-// Forward: x = L^{-1} b.  Task I (in ticket order): s = b_I - sum_{K<I} L_IK x_K; x_I = X_II s.
-// The factor is complete before this kernel starts, so tile operands are fetched ahead of
-// the wait on each solution block; only x_K itself is waited for.
-template <typename R>
-__global__ __launch_bounds__(kThreads) void k_trsv_fwd(
-    const R* __restrict__ Lt, const R* __restrict__ Linv, int T, const double* __restrict__ b,
-    double* __restrict__ x, SyncArea* sync, uint32_t* flags, int32_t* status,
-    const LMState* __restrict__ lm, int gate) {
-  __shared__ double sh[kThreads];
-  __shared__ double s_vec[64];
-  if (gated(lm, gate)) {
-    exit_and_reset(sync, flags, T);
-    return;
+// Triangular solves x = L^{-1} b (forward) and x = L^{-T} b (backward) on the tile-packed
+// factor, with the inverses X_II of the diagonal tiles:
+//   forward:  x_I = X_II (b_I - sum_{K<I} L_IK x_K),        blocks I = 0, 1, ..., T-1
+//   backward: x_I = X_II^T (b_I - sum_{K>I} L_KI^T x_K),    blocks I = T-1, ..., 0
+// Ticket 0 makes its workgroup the chain worker: it walks the blocks in solve order, keeps the
+// previous block of x in LDS and the two tiles it needs next (X of the next block and the
+// tile coupling it to the current one) in registers, so each step of the dependent chain is
+// two 64x64 products with no wait on another workgroup.  The other workgroups (helpers, one
+// per block from the third one on, in solve order) accumulate the contributions of all
+// blocks at distance >= 2 as their solutions appear and hand the partial sum to the worker.
+// FP64 vectors and accumulation; R-typed factor.
+template <typename R, bool FWD>
+__device__ __forceinline__ int solve_block(int T, int q) { return FWD ? q : T - 1 - q; }
+
+// Tile coupling block I to block K (K before I in solve order), and the thread's 16 operands:
+// forward reads row r of L_IK, backward reads column c of L_KI.
+template <typename R, bool FWD>
+__device__ __forceinline__ void load_coupling(const R* __restrict__ Lt, int T, int I, int K,
+                                              int rc, int part, R (&v)[16]) {
+  if (FWD) {
+    const R* p = Lt + (int64_t)tile_index(I, K, T) * 4096 + rc * 64 + part * 16;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = p[u];
+  } else {
+    const R* p = Lt + (int64_t)tile_index(K, I, T) * 4096 + (part * 16) * 64 + rc;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = p[u * 64];
   }
-  const int tid = threadIdx.x, r = tid & 63, part = tid >> 6;
-  for (;;) {
-    const uint32_t t = claim(sync);
-    if (t >= (uint32_t)T) break;
-    const int I = (int)t;
-    R xinv[16], cur[16], nxt[16];
-    const R* inv = Linv + (int64_t)I * 4096 + r * 64 + part * 16;
-#pragma unroll
-    for (int c = 0; c < 16; ++c) xinv[c] = inv[c];
-    if (I > 0) {
-      const R* tile = Lt + (int64_t)tile_index(I, 0, T) * 4096 + r * 64 + part * 16;
-#pragma unroll
-      for (int c = 0; c < 16; ++c) nxt[c] = tile[c];
-    }
-    double acc = 0.0;
-    bool ok = true;
-    for (int K = 0; K < I; ++K) {
-#pragma unroll
-      for (int c = 0; c < 16; ++c) cur[c] = nxt[c];
-      if (K + 1 < I) {
-        const R* tile = Lt + (int64_t)tile_index(I, K + 1, T) * 4096 + r * 64 + part * 16;
-#pragma unroll
-        for (int c = 0; c < 16; ++c) nxt[c] = tile[c];
-      }
-      if (ok) ok = wait_flag(flags + K, sync, status);
-      const double* xv = x + 64 * K + part * 16;
-#pragma unroll
-      for (int c = 0; c < 16; ++c) acc = fma((double)cur[c], xv[c], acc);
-    }
-    const double sum = reduce4(acc, sh);
-    if (tid < 64) s_vec[tid] = b[64 * I + tid] - sum;
-    __syncthreads();
-    double y = 0.0;
-#pragma unroll
-    for (int c = 0; c < 16; ++c) y = fma((double)xinv[c], s_vec[part * 16 + c], y);
-    const double xi = reduce4(y, sh);
-    if (tid < 64) x[64 * I + tid] = xi;
-    publish(flags + I);
-    __syncthreads();
-  }
-  exit_and_reset(sync, flags, T);
 }
 
-// Backward: x = L^{-T} b.  Task t solves block I = T-1-t: s = b_I - sum_{K>I} L_KI^T x_K;
-// x_I = X_II^T s.  With acc_out != null the result is also added into acc_out (d += e).
-template <typename R>
-__global__ __launch_bounds__(kThreads) void k_trsv_bwd(
+template <typename R, bool FWD>
+__device__ __forceinline__ void load_inverse(const R* __restrict__ Linv, int I, int rc, int part,
+                                             R (&v)[16]) {
+  const R* base = Linv + (int64_t)I * 4096;
+  if (FWD) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = base[rc * 64 + part * 16 + u];
+  } else {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = base[(part * 16 + u) * 64 + rc];
+  }
+}
+
+template <typename R, bool FWD>
+__global__ __launch_bounds__(kThreads) void k_trsv(
     const R* __restrict__ Lt, const R* __restrict__ Linv, int T, const double* __restrict__ b,
-    double* __restrict__ x, double* __restrict__ acc_out, SyncArea* sync, uint32_t* flags,
-    int32_t* status, const LMState* __restrict__ lm, int gate) {
+    double* __restrict__ x, double* __restrict__ acc_out, double* __restrict__ part_sum,
+    SyncArea* sync, uint32_t* flags, int32_t* status, const LMState* __restrict__ lm, int gate) {
   __shared__ double sh[kThreads];
   __shared__ double s_vec[64];
+  __shared__ double s_x[64];
+  uint32_t* xflags = flags;
+  uint32_t* pflags = flags + T;
   if (gated(lm, gate)) {
-    exit_and_reset(sync, flags, T);
+    exit_and_reset(sync, flags, 2 * T);
     return;
   }
-  const int tid = threadIdx.x, c = tid & 63, part = tid >> 6;
+  const int tid = threadIdx.x, rc = tid & 63, part = tid >> 6;
+  const uint32_t ntasks = 1u + (uint32_t)(T > 2 ? T - 2 : 0);
   for (;;) {
     const uint32_t t = claim(sync);
-    if (t >= (uint32_t)T) break;
-    const int I = T - 1 - (int)t;
-    R xinv[16], cur[16], nxt[16];
-    // (X_II^T s)[c] = sum_r X_II[r][c] s[r]; (L_KI^T x_K)[c] = sum_r L_KI[r][c] x_K[r]
-    const R* inv = Linv + (int64_t)I * 4096 + (part * 16) * 64 + c;
+    if (t >= ntasks) break;
+    if (t == 0) {
+      // chain worker: inv and nb hold X of the block at position q and its coupling to q-1,
+      // both fetched during the previous step
+      R inv[16], nb[16];
+      load_inverse<R, FWD>(Linv, solve_block<R, FWD>(T, 0), rc, part, inv);
+      bool ok = true;
+      for (int q = 0; q < T; ++q) {
+        const int I = solve_block<R, FWD>(T, q);
+        double pv = 0.0;
+        if (q >= 2) {
+          if (ok) ok = wait_flag(pflags + I, sync, status);
+          if (tid < 64) pv = part_sum[64 * I + tid];
+        }
+        double a = 0.0;
+        if (q >= 1) {
 #pragma unroll
-    for (int rr = 0; rr < 16; ++rr) xinv[rr] = inv[rr * 64];
-    if (I < T - 1) {
-      const R* tile = Lt + (int64_t)tile_index(T - 1, I, T) * 4096 + (part * 16) * 64 + c;
+          for (int u = 0; u < 16; ++u) a = fma((double)nb[u], s_x[part * 16 + u], a);
+        }
+        const double asum = reduce4(a, sh);
+        if (tid < 64) s_vec[tid] = b[64 * I + tid] - pv - asum;
+        __syncthreads();
+        double y = 0.0;
 #pragma unroll
-      for (int rr = 0; rr < 16; ++rr) nxt[rr] = tile[rr * 64];
-    }
-    double acc = 0.0;
-    bool ok = true;
-    for (int K = T - 1; K > I; --K) {
-#pragma unroll
-      for (int rr = 0; rr < 16; ++rr) cur[rr] = nxt[rr];
-      if (K - 1 > I) {
-        const R* tile = Lt + (int64_t)tile_index(K - 1, I, T) * 4096 + (part * 16) * 64 + c;
-#pragma unroll
-        for (int rr = 0; rr < 16; ++rr) nxt[rr] = tile[rr * 64];
+        for (int u = 0; u < 16; ++u) y = fma((double)inv[u], s_vec[part * 16 + u], y);
+        if (q + 1 < T) {
+          const int In = solve_block<R, FWD>(T, q + 1);
+          load_coupling<R, FWD>(Lt, T, In, I, rc, part, nb);
+          load_inverse<R, FWD>(Linv, In, rc, part, inv);
+        }
+        const double xi = reduce4(y, sh);
+        if (tid < 64) {
+          x[64 * I + tid] = xi;
+          s_x[tid] = xi;
+          if (acc_out) acc_out[64 * I + tid] += xi;
+        }
+        publish(xflags + I);
+        __syncthreads();
       }
-      if (ok) ok = wait_flag(flags + K, sync, status);
-      const double* xv = x + 64 * K + part * 16;
+    } else {
+      // helper for the block at solve position q = t + 1: contributions of positions <= q-2
+      const int q = (int)t + 1;
+      const int I = solve_block<R, FWD>(T, q);
+      R cur[16], nxt[16];
+      load_coupling<R, FWD>(Lt, T, I, solve_block<R, FWD>(T, 0), rc, part, nxt);
+      double acc = 0.0;
+      bool ok = true;
+      for (int qq = 0; qq <= q - 2; ++qq) {
+        const int K = solve_block<R, FWD>(T, qq);
 #pragma unroll
-      for (int rr = 0; rr < 16; ++rr) acc = fma((double)cur[rr], xv[rr], acc);
-    }
-    const double sum = reduce4(acc, sh);
-    if (tid < 64) s_vec[tid] = b[64 * I + tid] - sum;
-    __syncthreads();
-    double y = 0.0;
+        for (int u = 0; u < 16; ++u) cur[u] = nxt[u];
+        if (qq + 1 <= q - 2)
+          load_coupling<R, FWD>(Lt, T, I, solve_block<R, FWD>(T, qq + 1), rc, part, nxt);
+        if (ok) ok = wait_flag(xflags + K, sync, status);
+        const double* xv = x + 64 * K + part * 16;
 #pragma unroll
-    for (int rr = 0; rr < 16; ++rr) y = fma((double)xinv[rr], s_vec[part * 16 + rr], y);
-    const double xi = reduce4(y, sh);
-    if (tid < 64) {
-      x[64 * I + tid] = xi;
-      if (acc_out) acc_out[64 * I + tid] += xi;
+        for (int u = 0; u < 16; ++u) acc = fma((double)cur[u], xv[u], acc);
+      }
+      const double sum = reduce4(acc, sh);
+      if (tid < 64) part_sum[64 * I + tid] = sum;
+      publish(pflags + I);
+      __syncthreads();
     }
-    publish(flags + I);
-    __syncthreads();
   }
-  exit_and_reset(sync, flags, T);
+  exit_and_reset(sync, flags, 2 * T);
 }
 
 // Refinement residual s = g - (H + mu I) d in FP64 from the FP32/FP64 column-major lower
@@ -942,29 +1007,34 @@ size_t chol_smem_bytes() {
 
 template <typename R>
 hipError_t launch_cholesky(const R* Hc, int ld, int n_pad, const double* mu_dev, double mu_host,
-                           const double* g, double* y, R* Lt, R* Linv, SyncArea* sync,
+                           const double* g, double* y, R* Lt, R* Linv, R* part, SyncArea* sync,
                            uint32_t* flags, uint32_t* yflags, int32_t* status, hipStream_t st,
                            int n_wg) {
   const int T = n_pad / 64;
   const int ntasks = (int)chol_tasks(T);
-  const int grid = n_wg < ntasks ? n_wg : ntasks;
+  // at least two workgroups: the diagonal worker and one for the other tasks
+  int grid = n_wg < ntasks ? n_wg : ntasks;
+  if (grid < 2) grid = 2;
   hipLaunchKernelGGL(k_cholesky<R>, dim3(grid), dim3(kThreads), chol_smem_bytes<R>(), st, Hc,
-                     (int64_t)ld, T, mu_dev, mu_host, g, y, Lt, Linv, sync, flags, yflags, status);
+                     (int64_t)ld, T, mu_dev, mu_host, g, y, Lt, Linv, part, sync, flags, yflags,
+                     status);
   return hipGetLastError();
 }
 
 template <typename R>
 hipError_t launch_trsv(bool forward, const R* Lt, const R* Linv, int n_pad, const double* b,
-                       double* x, double* acc_out, SyncArea* sync, uint32_t* flags,
-                       int32_t* status, const LMState* lm, int gate, hipStream_t st) {
+                       double* x, double* acc_out, double* part_sum, SyncArea* sync,
+                       uint32_t* flags, int32_t* status, const LMState* lm, int gate,
+                       hipStream_t st) {
   const int T = n_pad / 64;
-  const int grid = T < 256 ? T : 256;
+  const int ntasks = 1 + (T > 2 ? T - 2 : 0);
+  const int grid = ntasks < 256 ? ntasks : 256;
   if (forward)
-    hipLaunchKernelGGL(k_trsv_fwd<R>, dim3(grid), dim3(kThreads), 0, st, Lt, Linv, T, b, x, sync,
-                       flags, status, lm, gate);
+    hipLaunchKernelGGL((k_trsv<R, true>), dim3(grid), dim3(kThreads), 0, st, Lt, Linv, T, b, x,
+                       acc_out, part_sum, sync, flags, status, lm, gate);
   else
-    hipLaunchKernelGGL(k_trsv_bwd<R>, dim3(grid), dim3(kThreads), 0, st, Lt, Linv, T, b, x,
-                       acc_out, sync, flags, status, lm, gate);
+    hipLaunchKernelGGL((k_trsv<R, false>), dim3(grid), dim3(kThreads), 0, st, Lt, Linv, T, b, x,
+                       acc_out, part_sum, sync, flags, status, lm, gate);
   return hipGetLastError();
 }
 
@@ -994,11 +1064,11 @@ hipError_t set_chol_smem_attr() {
 
 #define DDC_INST(R)                                                                           \
   template hipError_t launch_cholesky<R>(const R*, int, int, const double*, double,             \
-                                         const double*, double*, R*, R*, SyncArea*, uint32_t*, \
-                                         uint32_t*, int32_t*, hipStream_t, int);               \
+                                         const double*, double*, R*, R*, R*, SyncArea*,        \
+                                         uint32_t*, uint32_t*, int32_t*, hipStream_t, int);    \
   template hipError_t launch_trsv<R>(bool, const R*, const R*, int, const double*, double*,    \
-                                     double*, SyncArea*, uint32_t*, int32_t*, const LMState*,  \
-                                     int, hipStream_t);                                        \
+                                     double*, double*, SyncArea*, uint32_t*, int32_t*,         \
+                                     const LMState*, int, hipStream_t);                        \
   template hipError_t launch_refine_resid<R>(const R*, int, int, const double*, const double*, \
                                              const double*, double*, double*, double*, double*, \
                                              const LMState*, int, hipStream_t);

@@ -134,7 +134,8 @@ def serve_measure(n_requests=200, n_slots=4, seed=0, precision="mixed"):
 
 
 def lbfgs_measure(seed=0, n_iter=200):
-    """Gradient-based solve (adjoint kernel + torch L-BFGS) vs LM on the N=256 workload."""
+    """Gradient-based solve (adjoint kernel + torch L-BFGS, plain and with a diagonal Jacobi
+    change of variables) vs LM on the N=256 workload."""
     import torch
     from paper_1910_13908_amd import synth, ddcal as dd, autograd as ag
     cfg = synth.CONFIGS["n256_k10"]
@@ -155,12 +156,22 @@ def lbfgs_measure(seed=0, n_iter=200):
         Jl, costs = ag.lbfgs_calibrate(prob, J0, n_iter=n_iter)
         torch.cuda.synchronize()
         t_l = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        scale = ag.jacobi_scaling(prob, J0)
+        Jp, costs_p = ag.lbfgs_calibrate(prob, J0, n_iter=n_iter, scaling=scale)
+        torch.cuda.synchronize()
+        t_p = time.perf_counter() - t0
         J = J0.clone()
         t0 = time.perf_counter()
         infos = ctx.calibrate(obs, sky, V, J, cfg.n_sweeps, dd.default_lm_opts(n_iter=cfg.n_lm, precision=prec))
         torch.cuda.synchronize()
         t_m = time.perf_counter() - t0
-        out[pname] = {"lbfgs_final_cost": costs[-1], "lbfgs_s": t_l, "lbfgs_iters": n_iter,
+        f0 = ctx.residual(obs, ob.K, V, coh, J0, prec, None)
+        out[pname] = {"cost_at_start": f0,
+                      "lbfgs_final_cost": costs[-1], "lbfgs_s": t_l, "lbfgs_iters": n_iter,
+                      "lbfgs_cost_trace": [costs[i] for i in (0, 9, 49, 99, n_iter - 1)],
+                      "jacobi_lbfgs_final_cost": costs_p[-1], "jacobi_lbfgs_s": t_p,
+                      "jacobi_lbfgs_cost_trace": [costs_p[i] for i in (0, 9, 49, 99, n_iter - 1)],
                       "lm_final_cost": infos[-1][-1].cost, "lm_s": t_m,
                       "lm_iters": cfg.n_sweeps * ob.K * cfg.n_lm,
                       "cost_at_truth": ctx.residual(obs, ob.K, V, coh, Jt, prec, None)}
@@ -253,6 +264,29 @@ def copy_measure(mib=1024, reps=5):
     el = time.perf_counter() - t0
     return {"bytes_read_per_copy": n * 4, "bytes_written_per_copy": n * 4, "copies": reps + 1,
             "gbs": 2 * n * 4 * reps / el / 1e9}
+
+
+def _hbm_roofline(kernel, launches, total_ms, algo_bytes):
+    """Achieved algorithmic GB/s of an HBM-bound kernel from the live event timers, with the
+    HBM bytes per launch measured by rocprofv3 (profiles/) while that kernel's source is the one
+    profiled, else traffic null."""
+    import hashlib
+    out = {"bound": "hbm", "kernel": kernel, "unit": "GB/s", "peak": PEAK["hbm_gbs"],
+           "achieved": None, "frac": None, "traffic": None}
+    if launches and total_ms > 0:
+        out["achieved"] = algo_bytes / (total_ms * 1e-3) / 1e9
+        out["frac"] = out["achieved"] / PEAK["hbm_gbs"]
+        out["avg_us"] = 1e3 * total_ms / launches
+    try:
+        prof = json.load(open(os.path.join(ROOT, "profiles", "hbm_traffic_n512_k20_mixed.json")))
+        k = prof["kernels"][kernel]
+        src = open(os.path.join(ROOT, k["source"]), "rb").read()
+        if hashlib.sha256(src).hexdigest() == k["sha256"]:
+            out["traffic"] = k["fetch_bytes"] + k["write_bytes"]
+            out["traffic_source"] = "profiles/hbm_traffic_n512_k20_mixed.json"
+    except (OSError, KeyError, ValueError):
+        pass
+    return out
 
 
 def cpu_baseline(cfg, seed):
@@ -374,7 +408,7 @@ def main():
     kernel_ms = {k: {"launches": v[0], "avg_us": 1e3 * v[1] / max(v[0], 1),
                      "share_of_step": v[1] / (1e3 * elapsed) if elapsed > 0 else 0.0}
                  for k, v in timers.items()}
-    nb, msb, byb = timers["build"]
+    n_tr, ms_tr, by_tr = timers["trial"]
 
     out = {
         "metric": "LM iters/s", "value": value, "unit": "LM iters/s", "n_gpus": 1,
@@ -391,11 +425,16 @@ def main():
         "roofline": {"bound": "mfma", "kernel": "k_cholesky", "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": None,
+                     "traffic_note": "HBM counters could not be collected on this kernel (the "
+                                     "profiler process dies at the next launch); see "
+                                     "roofline_hbm and profiles/ for measured traffic",
                      "per_launch": f"(8N)^3/3 = {(8 * N) ** 3 / 3:.3e} flop per factorisation, "
                                    f"avg {1e3 * ms_ch / max(n_ch, 1):.1f} us over {n_ch} launches"},
         "predict_gvis_per_s": gvis,
         "predict_gterms_per_s": terms / (ms_pr * 1e-3) / 1e9 if ms_pr > 0 else 0.0,
-        "build_gbs": byb / (msb * 1e-3) / 1e9 if msb > 0 else 0.0,
+        # the trial cost runs in every LM iteration (the build is skipped after a rejection,
+        # so its average over launches would not be a bandwidth)
+        "roofline_hbm": _hbm_roofline("k_trial_cost", n_tr, ms_tr, by_tr),
         "kernels": kernel_ms,
         "final_total_cost": final_cost,
     }

@@ -133,13 +133,15 @@ hipError_t launch_cholesky(const R* Hc, int ld, int n_pad, const double* mu_dev,
                            const double* g, double* y, R* Lt, R* Linv, R* part, SyncArea* sync,
                            uint32_t* flags, uint32_t* yflags, int32_t* status, hipStream_t st,
                            int n_wg);
-// x = L^{-1} b (forward) or L^{-T} b (backward); acc_out (nullable) += x; part_sum: n_pad
-// doubles of scratch; flags: 2 T entries.
+// x = L^{-1} b (forward) or L^{-T} b (backward); acc_out (nullable) += x.  psum and xpub: 64 T
+// message slots each, holding kEmpty before the launch (they hold it again after it).
 template <typename R>
 hipError_t launch_trsv(bool forward, const R* Lt, const R* Linv, int n_pad, const double* b,
-                       double* x, double* acc_out, double* part_sum, SyncArea* sync,
-                       uint32_t* flags, int32_t* status, const LMState* lm, int gate,
+                       double* x, double* acc_out, uint64_t* psum, uint64_t* xpub,
+                       SyncArea* sync, int32_t* status, const LMState* lm, int gate,
                        hipStream_t st);
+// Fill n message slots with kEmpty.
+hipError_t launch_fill_empty(uint64_t* p, int n, hipStream_t st);
 // s = g - (H + mu I) d (FP64) via per-tile partials prow/pcol ([T(T+1)/2][64] each).
 template <typename R>
 hipError_t launch_refine_resid(const R* Hc, int ld, int n_pad, const double* mu_dev,

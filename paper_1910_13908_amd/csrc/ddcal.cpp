@@ -18,7 +18,7 @@ using namespace ddc;
 namespace {
 
 constexpr int kMaxTiles = 512;                  // n_pad <= 32768 (N <= 4096 stations)
-constexpr size_t kSyncBytes = 1u << 20;
+constexpr size_t kSyncBytes = 2u << 20;        // [0, 1 MiB) zeroed; [1 MiB, 2 MiB) solve messages
 
 enum Timer { T_CHOL = 0, T_PREDICT, T_BUILD, T_TRSV, T_TRIAL, T_MODEL, T_REFINE, T_ADJOINT, T_COUNT };
 
@@ -61,6 +61,9 @@ struct ddc_ctx {
   uint32_t* chol_flags() { return reinterpret_cast<uint32_t*>(sync + 1024); }
   uint32_t* fwd_flags() { return chol_flags() + kMaxTiles * (kMaxTiles + 1) / 2 + kMaxTiles; }
   uint32_t* bwd_flags() { return fwd_flags() + 2 * kMaxTiles; }
+  // triangular-solve message arrays (partial sums, solution blocks), kEmpty between solves
+  uint64_t* solve_psum() { return reinterpret_cast<uint64_t*>(sync + (1u << 20)); }
+  uint64_t* solve_xpub() { return solve_psum() + 64 * kMaxTiles; }
 };
 
 namespace {
@@ -220,7 +223,7 @@ ddc_status obs_dev(ddc_ctx* c, const ddc_obs* o, ObsDev& d) {
 struct SolveBufs {
   int n, n_pad, T, ld;
   void *Hc, *Lt, *Linv, *part, *cpart;
-  double *g, *diag, *d, *y, *s, *e, *cost_part, *s_part, *scalar, *prow, *pcol, *tpart;
+  double *g, *diag, *d, *y, *s, *e, *cost_part, *s_part, *scalar, *prow, *pcol;
   size_t h_off;
 };
 
@@ -244,7 +247,6 @@ void layout_solve(Bump& bp, SolveBufs& b, int n, size_t es, int64_t B, int64_t n
   offs.push_back(bp.take(ntiles * 64 * sizeof(double)));               // prow
   offs.push_back(bp.take(ntiles * 64 * sizeof(double)));               // pcol
   offs.push_back(bp.take((size_t)b.T * 2 * 4096 * es));                 // Cholesky partial sums
-  offs.push_back(bp.take(np * sizeof(double)));                         // solve partial sums
 }
 
 void bind_solve(ddc_ctx* c, SolveBufs& b, const std::vector<size_t>& o) {
@@ -265,7 +267,6 @@ void bind_solve(ddc_ctx* c, SolveBufs& b, const std::vector<size_t>& o) {
   b.prow = reinterpret_cast<double*>(w + o[13]);
   b.pcol = reinterpret_cast<double*>(w + o[14]);
   b.cpart = w + o[15];
-  b.tpart = reinterpret_cast<double*>(w + o[16]);
   b.h_off = o[0];
 }
 
@@ -300,8 +301,8 @@ ddc_status enqueue_solve(ddc_ctx* c, SolveBufs& b, LMState* lm, int refine_max, 
   }));
   const double tri_bytes = (double)b.n_pad * (b.n_pad + 64) / 2 * sizeof(R);
   DDCCK(timed(c, T_TRSV, tri_bytes, [&] {
-    return launch_trsv<R>(false, Lt, Li, b.n_pad, b.y, b.d, nullptr, b.tpart, c->area(2),
-                          c->bwd_flags(), &lm->timeout, lm, 1, st);
+    return launch_trsv<R>(false, Lt, Li, b.n_pad, b.y, b.d, nullptr, c->solve_psum(),
+                          c->solve_xpub(), c->area(2), &lm->timeout, lm, 1, st);
   }));
   for (int r = 0; r < refine_max; ++r) {
     DDCCK(timed(c, T_REFINE, (double)b.n_pad * b.n_pad * sizeof(R), [&] {
@@ -310,12 +311,12 @@ ddc_status enqueue_solve(ddc_ctx* c, SolveBufs& b, LMState* lm, int refine_max, 
     }));
     HIPCK(launch_refine_ctrl(lm, b.s_part, b.T, tol * tol, st));
     DDCCK(timed(c, T_TRSV, tri_bytes, [&] {
-      return launch_trsv<R>(true, Lt, Li, b.n_pad, b.s, b.y, nullptr, b.tpart, c->area(1),
-                            c->fwd_flags(), &lm->timeout, lm, 2, st);
+      return launch_trsv<R>(true, Lt, Li, b.n_pad, b.s, b.y, nullptr, c->solve_psum(),
+                            c->solve_xpub(), c->area(1), &lm->timeout, lm, 2, st);
     }));
     DDCCK(timed(c, T_TRSV, tri_bytes, [&] {
-      return launch_trsv<R>(false, Lt, Li, b.n_pad, b.y, b.e, b.d, b.tpart, c->area(2),
-                            c->bwd_flags(), &lm->timeout, lm, 2, st);
+      return launch_trsv<R>(false, Lt, Li, b.n_pad, b.y, b.e, b.d, c->solve_psum(),
+                            c->solve_xpub(), c->area(2), &lm->timeout, lm, 2, st);
     }));
   }
   return DDC_OK;
@@ -403,8 +404,9 @@ ddc_status ddc_create(ddc_ctx** out, int32_t device) {
   ddc_ctx* c = new ddc_ctx();
   c->device = device;
   if (hipMalloc(&c->sync, kSyncBytes) != hipSuccess ||
-      hipMemset(c->sync, 0, kSyncBytes) != hipSuccess || set_chol_smem_attr() != hipSuccess ||
-      hipDeviceSynchronize() != hipSuccess) {
+      hipMemset(c->sync, 0, 1u << 20) != hipSuccess ||
+      launch_fill_empty(c->solve_psum(), 2 * 64 * kMaxTiles, nullptr) != hipSuccess ||
+      set_chol_smem_attr() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
     (void)hipGetLastError();
     if (c->sync) (void)hipFree(c->sync);
     delete c;

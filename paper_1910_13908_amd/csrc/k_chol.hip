@@ -305,9 +305,12 @@ __device__ __forceinline__ void wave_sync_lds() {
 }
 
 // Wave 0: factor columns 16P..16P+15 (rows >= 16P) in place; returns nonzero on a bad pivot.
-// Lane i keeps its panel row in registers; row c of the panel (needed by every lane for
-// column c) is broadcast from lane c with readlane, so the serial column loop never goes
-// through LDS.  The finished panel is written back once at the end.
+// Lane i keeps its panel row in registers.  Right-looking inside the panel: once column j is
+// scaled, each later column jj takes its rank-1 update with the multiplier L[16P+jj][j],
+// broadcast from lane 16P+jj by readlane; the broadcasts of one column are independent, so
+// only the pivot broadcast, the rsq and one update sit on the serial chain.  The pivot lane
+// holds d itself, so scaling every lane by rsq(d) leaves sqrt(d) on the diagonal.  The whole
+// panel is written back: entries above the diagonal of the tile are never read.
 template <typename R, int P>
 __device__ int panel_factor(R* A, R* rdiag) {
   constexpr int STR = Mfma<R>::STR;
@@ -316,33 +319,21 @@ __device__ int panel_factor(R* A, R* rdiag) {
   R a[16];
 #pragma unroll
   for (int j = 0; j < 16; ++j) a[j] = A[i * STR + c0 + j];
-  int bad = 0;
-  R rd = (R)0;
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
-    const int c = c0 + j;
-    R d0 = 0, d1 = 0;
+    const R r = rsq_full(bcast_lane(a[j], c0 + j));
+    a[j] *= r;
+    if (i == 0) rdiag[c0 + j] = r;
 #pragma unroll
-    for (int k = 0; k < j; k += 2) {
-      d0 = fma(a[k], bcast_lane(a[k], c), d0);
-      if (k + 1 < j) d1 = fma(a[k + 1], bcast_lane(a[k + 1], c), d1);
-    }
-    const R x = a[j] - (d0 + d1);
-    R d = bcast_lane(x, c);
-    if (!(d > (R)0) || !(d < (R)INFINITY)) {
-      bad = 1;
-      d = (R)1;
-    }
-    const R r = rsq_full(d);
-    a[j] = (i == c) ? d * r : x * r;
-    if (i == c) rd = r;
+    for (int jj = j + 1; jj < 16; ++jj) a[jj] = fma(-a[j], bcast_lane(a[j], c0 + jj), a[jj]);
   }
-  // rows above the panel keep their (upper-triangle) values; rows at or below write L
 #pragma unroll
-  for (int j = 0; j < 16; ++j)
-    if (i >= c0 + j) A[i * STR + c0 + j] = a[j];
-  if (i >= c0 && i < c0 + 16) rdiag[i] = rd;
-  return bad;
+  for (int j = 0; j < 16; ++j) A[i * STR + c0 + j] = a[j];
+  // a pivot d <= 0, inf or nan leaves 1/sqrt(d) outside (0, inf): one check per column after
+  // the panel instead of a lane mask per column inside it (the values are then garbage, and
+  // the caller discards them on the flag)
+  const R rc = rdiag[c0 + (i & 15)];
+  return __any(!(rc > (R)0 && rc < (R)INFINITY)) ? 1 : 0;
 }
 
 // All waves: A[r][c] -= sum_{k in panel P} A[r][k] A[c][k] for the lower 16x16 blocks right
@@ -377,8 +368,24 @@ __device__ void panel_update(R* A) {
   }
 }
 
-// Factor the tile in A (lower triangle) in place and write X = L^{-1} into X.  Returns
-// nonzero (in every thread) if a pivot was not positive.
+// Factor the tile in A (lower triangle) in place and write X = L^{-1} into X; the blocks of X
+// above its block diagonal must already hold zeros (zero_upper_blocks).  Returns nonzero (in
+// every thread) if a pivot was not positive.
+// Zero the six 16x16 blocks above the block diagonal of a 64x64 LDS tile.
+template <typename R>
+__device__ __forceinline__ void zero_upper_blocks(R* X) {
+  constexpr int STR = Mfma<R>::STR;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const int e = threadIdx.x + k * kThreads;       // 6 x 256 elements
+    const int blk = e >> 8, r = (e >> 4) & 15, c = e & 15;
+    // blk 0..5 -> (row block, column block) = (0,1) (0,2) (0,3) (1,2) (1,3) (2,3)
+    const int bi = blk < 3 ? 0 : (blk < 5 ? 1 : 2);
+    const int bj = blk < 3 ? blk + 1 : (blk < 5 ? blk - 1 : 3);
+    X[(16 * bi + r) * STR + 16 * bj + c] = (R)0;
+  }
+}
+
 template <typename R>
 __device__ int cholinv_tile(R* A, R* X, R* rdiag) {
   constexpr int STR = Mfma<R>::STR;
@@ -402,12 +409,9 @@ __device__ int cholinv_tile(R* A, R* X, R* rdiag) {
     bad |= panel_factor<R, 3>(A, rdiag);
     if (lane == 0) s_bad = bad;
   }
-  // inverse of the diagonal 16x16 blocks: wave w takes block w, lane c < 16 column c
-  for (int e = tid; e < 64 * 64; e += kThreads) {
-    const int r = e >> 6, c = e & 63;
-    if ((c >> 4) > (r >> 4)) X[r * STR + c] = (R)0;
-  }
   __syncthreads();
+  // inverse of the diagonal 16x16 blocks: wave w takes block w, lane c < 16 column c; the
+  // right-hand side e_c is formed arithmetically (no per-row lane masks)
   if (lane < 16) {
     const int b0 = 16 * wv, c = lane;
     R x[16];
@@ -420,7 +424,8 @@ __device__ int cholinv_tile(R* A, R* X, R* rdiag) {
         d0 = fma(rowi[k], x[k], d0);
         if (k + 1 < i) d1 = fma(rowi[k + 1], x[k + 1], d1);
       }
-      x[i] = ((i == c ? (R)1 : (R)0) - (d0 + d1)) * rdiag[b0 + i];
+      const R e = (R)(1 - min(abs(i - c), 1));
+      x[i] = (e - (d0 + d1)) * rdiag[b0 + i];
     }
 #pragma unroll
     for (int i = 0; i < 16; ++i) X[(b0 + i) * STR + b0 + c] = x[i];
@@ -510,7 +515,12 @@ __device__ __forceinline__ void acc_load_h(typename Mfma<R>::acc_t (&acc)[2][2],
         const int r = qr * 32 + bi * 16 + out_row<R>(lane, v);
         const int c = qc * 32 + bj * 16 + out_col(lane, v);
         R h = Hc[(int64_t)(64 * J + c) * ld + 64 * I + r];
-        if (I == J && r == c) h = (R)((double)h + mu);
+        if (I == J) {
+          // mu on the diagonal only, selected arithmetically: a per-element lane mask here
+          // would be hoisted out of the step loop and exhaust the scalar registers
+          const double on = (double)(1 - min(abs(r - c), 1));
+          h = (R)((double)h + mu * on);
+        }
         acc[bi][bj][v] = h;
       }
 }
@@ -641,6 +651,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
       R* Xprev = lds + TILE;
       R* Xcur = lds + 2 * TILE;
       R* Lbuf = lds + 3 * TILE;
+      zero_upper_blocks<R>(Xprev);
+      zero_upper_blocks<R>(Xcur);
       for (int st = 0; st < T; ++st) {
         acc_t accd[2][2];
         acc_load_h<R>(accd, Hc, ld, st, st, mu, qr, qc);
@@ -786,14 +798,46 @@ __device__ __forceinline__ double reduce4(double v, double* sh) {
 // factor, with the inverses X_II of the diagonal tiles:
 //   forward:  x_I = X_II (b_I - sum_{K<I} L_IK x_K),        blocks I = 0, 1, ..., T-1
 //   backward: x_I = X_II^T (b_I - sum_{K>I} L_KI^T x_K),    blocks I = T-1, ..., 0
-// Ticket 0 makes its workgroup the chain worker: it walks the blocks in solve order, keeps the
-// previous block of x in LDS and the two tiles it needs next (X of the next block and the
-// tile coupling it to the current one) in registers, so each step of the dependent chain is
-// two 64x64 products with no wait on another workgroup.  The other workgroups (helpers, one
-// per block from the third one on, in solve order) accumulate the contributions of all
-// blocks at distance >= 2 as their solutions appear and hand the partial sum to the worker.
-// FP64 vectors and accumulation; R-typed factor.
-template <typename R, bool FWD>
+// Ticket 0 makes its workgroup the chain worker: it walks the blocks in solve order, applies
+// the kChainD-1 nearest blocks itself (their solutions in an LDS ring, the tiles that couple
+// them prefetched into registers one step ahead) and so never waits on another workgroup for
+// them.  The other workgroups (helpers, one per block from solve position kChainD on)
+// accumulate the contributions of all blocks at distance >= kChainD as their solutions
+// appear and hand the 64-entry partial sum to the worker, which has kChainD-1 steps of slack.
+// Hand-offs carry the data itself: solution blocks and partial sums travel through two
+// message arrays written and read with agent-scope relaxed 64-bit atomics, and a slot that
+// still holds kEmpty (a signalling-NaN payload that no arithmetic result carries) is not
+// ready yet.  So there is no fence or flag on the chain.  The worker fetches the partial sum
+// of the block two steps ahead.  The last workgroup out restores kEmpty in both arrays.
+constexpr int kChainD = 4;
+constexpr uint64_t kEmpty = 0x7FF4DD0000000001ull;
+
+__device__ __forceinline__ uint64_t msg_get(uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void msg_put(uint64_t* p, double v) {
+  __hip_atomic_store(p, (uint64_t)__double_as_longlong(v), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Per-lane bounded poll of one message slot; on abort or time-out returns kEmpty (the caller
+// carries on with garbage; the status word reports the failure).
+__device__ uint64_t msg_wait(uint64_t* p, SyncArea* sync, int32_t* status) {
+  uint32_t spins = 0;
+  uint64_t m;
+  while ((m = msg_get(p)) == kEmpty) {
+    if (__hip_atomic_load(&sync->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
+    if (++spins > kSpinLimit) {
+      __hip_atomic_store(&sync->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (status) atomicOr(status, 2);
+      break;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+  return m;
+}
+
+template <bool FWD>
 __device__ __forceinline__ int solve_block(int T, int q) { return FWD ? q : T - 1 - q; }
 
 // Tile coupling block I to block K (K before I in solve order), and the thread's 16 operands:
@@ -825,89 +869,175 @@ __device__ __forceinline__ void load_inverse(const R* __restrict__ Linv, int I, 
   }
 }
 
+// Leave the solve: the last workgroup out restores kEmpty in the message arrays (unless the
+// launch was gated and wrote none) and clears the counters.
+__device__ void trsv_exit(SyncArea* sync, uint64_t* psum, uint64_t* xpub, int n, bool dirty) {
+  __shared__ int s_last;
+  __threadfence();      // this workgroup's message stores land before it is counted out
+  __syncthreads();
+  if (threadIdx.x == 0) s_last = (atomicAdd(&sync->exited, 1u) == gridDim.x - 1);
+  __syncthreads();
+  if (s_last) {
+    if (dirty) {
+      for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        __hip_atomic_store(psum + i, kEmpty, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(xpub + i, kEmpty, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    if (threadIdx.x == 0) {
+      sync->ticket = 0u;
+      sync->exited = 0u;
+      sync->abort = 0u;
+    }
+    __threadfence();
+  }
+}
+
 template <typename R, bool FWD>
 __global__ __launch_bounds__(kThreads) void k_trsv(
     const R* __restrict__ Lt, const R* __restrict__ Linv, int T, const double* __restrict__ b,
-    double* __restrict__ x, double* __restrict__ acc_out, double* __restrict__ part_sum,
-    SyncArea* sync, uint32_t* flags, int32_t* status, const LMState* __restrict__ lm, int gate) {
+    double* __restrict__ x, double* __restrict__ acc_out, uint64_t* psum, uint64_t* xpub,
+    SyncArea* sync, int32_t* status, const LMState* __restrict__ lm, int gate) {
   __shared__ double sh[kThreads];
   __shared__ double s_vec[64];
-  __shared__ double s_x[64];
-  uint32_t* xflags = flags;
-  uint32_t* pflags = flags + T;
+  __shared__ double s_x[kChainD - 1][64];
   if (gated(lm, gate)) {
-    exit_and_reset(sync, flags, 2 * T);
+    trsv_exit(sync, psum, xpub, 64 * T, false);
     return;
   }
   const int tid = threadIdx.x, rc = tid & 63, part = tid >> 6;
-  const uint32_t ntasks = 1u + (uint32_t)(T > 2 ? T - 2 : 0);
+  const uint32_t ntasks = 1u + (uint32_t)(T > kChainD ? T - kChainD : 0);
   for (;;) {
     const uint32_t t = claim(sync);
     if (t >= ntasks) break;
     if (t == 0) {
-      // chain worker: inv and nb hold X of the block at position q and its coupling to q-1,
-      // both fetched during the previous step
-      R inv[16], nb[16];
-      load_inverse<R, FWD>(Linv, solve_block<R, FWD>(T, 0), rc, part, inv);
-      bool ok = true;
-      for (int q = 0; q < T; ++q) {
-        const int I = solve_block<R, FWD>(T, q);
+      // chain worker; inv, nb, bq and aq hold the operands of position q, fetched during
+      // step q-1; mq holds the partial-sum message of position q, mq1 that of q+1
+      // The prefetches are unconditional, with positions clamped into range (the values
+      // fetched for a position that does not exist are never used): a conditional load
+      // would make the wave wait for it at the join instead of at its use one step later.
+      // The loop is unrolled by two with slots A and B for the scalars fetched ahead (the
+      // right-hand side, the accumulation target and the partial-sum message), so no
+      // fetched value is copied across the back-edge, which would also force the wait.
+      R inv[16], nb[kChainD - 1][16];
+      const double* ap = acc_out ? acc_out : b;
+      const int lt = tid & 63;
+      load_inverse<R, FWD>(Linv, solve_block<FWD>(T, 0), rc, part, inv);
+      double bA = b[64 * solve_block<FWD>(T, 0) + lt], bB = 0.0;
+      double aA = ap[64 * solve_block<FWD>(T, 0) + lt], aB = 0.0;
+      uint64_t mA = kEmpty, mB = kEmpty;
+      auto step = [&](int q, uint64_t& m, double& b_use, double& b_fill, double& a_use,
+                      double& a_fill) {
+        const int I = solve_block<FWD>(T, q);
         double pv = 0.0;
-        if (q >= 2) {
-          if (ok) ok = wait_flag(pflags + I, sync, status);
-          if (tid < 64) pv = part_sum[64 * I + tid];
+        if (q >= kChainD && tid < 64) {
+          uint64_t mm = m;
+          if (mm == kEmpty) mm = msg_wait(psum + 64 * I + tid, sync, status);
+          pv = __longlong_as_double((long long)mm);
         }
+        // the message slot of position q is refilled with that of position q + 2
+        m = msg_get(psum + 64 * solve_block<FWD>(T, q + 2 < T ? q + 2 : T - 1) + lt);
         double a = 0.0;
-        if (q >= 1) {
 #pragma unroll
-          for (int u = 0; u < 16; ++u) a = fma((double)nb[u], s_x[part * 16 + u], a);
+        for (int d = 0; d < kChainD - 1; ++d) {
+          if (q - 1 - d >= 0) {
+            const double* xs = s_x[(q - 1 - d) % (kChainD - 1)] + part * 16;
+#pragma unroll
+            for (int u = 0; u < 16; ++u) a = fma((double)nb[d][u], xs[u], a);
+          }
         }
         const double asum = reduce4(a, sh);
-        if (tid < 64) s_vec[tid] = b[64 * I + tid] - pv - asum;
+        if (tid < 64) s_vec[tid] = b_use - pv - asum;
         __syncthreads();
         double y = 0.0;
 #pragma unroll
         for (int u = 0; u < 16; ++u) y = fma((double)inv[u], s_vec[part * 16 + u], y);
-        if (q + 1 < T) {
-          const int In = solve_block<R, FWD>(T, q + 1);
-          load_coupling<R, FWD>(Lt, T, In, I, rc, part, nb);
+        {
+          const int qn = q + 1 < T ? q + 1 : q;
+          const int In = solve_block<FWD>(T, qn);
           load_inverse<R, FWD>(Linv, In, rc, part, inv);
+#pragma unroll
+          for (int d = 0; d < kChainD - 1; ++d)
+            load_coupling<R, FWD>(Lt, T, In, solve_block<FWD>(T, q - d >= 0 ? q - d : 0), rc, part, nb[d]);
+          b_fill = b[64 * In + lt];
+          a_fill = ap[64 * In + lt];
         }
         const double xi = reduce4(y, sh);
         if (tid < 64) {
           x[64 * I + tid] = xi;
-          s_x[tid] = xi;
-          if (acc_out) acc_out[64 * I + tid] += xi;
+          s_x[q % (kChainD - 1)][tid] = xi;
+          msg_put(xpub + 64 * I + tid, xi);
+          if (acc_out) acc_out[64 * I + tid] = a_use + xi;
         }
-        publish(xflags + I);
         __syncthreads();
+      };
+      for (int q = 0; q < T; q += 2) {
+        step(q, mA, bA, bB, aA, aB);
+        if (q + 1 < T) step(q + 1, mB, bB, bA, aB, aA);
       }
     } else {
-      // helper for the block at solve position q = t + 1: contributions of positions <= q-2
-      const int q = (int)t + 1;
-      const int I = solve_block<R, FWD>(T, q);
-      R cur[16], nxt[16];
-      load_coupling<R, FWD>(Lt, T, I, solve_block<R, FWD>(T, 0), rc, part, nxt);
+      // helper for the block at solve position q = t + kChainD - 1: contributions of
+      // positions 0 .. q-kChainD, two solution blocks fetched per poll
+      const int q = (int)t + kChainD - 1;
+      const int I = solve_block<FWD>(T, q);
+      const int last = q - kChainD;
+      R c0[16], c1[16], n0[16], n1[16];
+      // unconditional prefetches with clamped positions, as in the worker
+      load_coupling<R, FWD>(Lt, T, I, solve_block<FWD>(T, 0), rc, part, n0);
+      load_coupling<R, FWD>(Lt, T, I, solve_block<FWD>(T, last >= 1 ? 1 : 0), rc, part, n1);
       double acc = 0.0;
-      bool ok = true;
-      for (int qq = 0; qq <= q - 2; ++qq) {
-        const int K = solve_block<R, FWD>(T, qq);
+      bool live = true;
+      for (int k0 = 0; k0 <= last; k0 += 2) {
+        const bool two = k0 + 1 <= last;
+        const int K0 = solve_block<FWD>(T, k0), K1 = solve_block<FWD>(T, two ? k0 + 1 : k0);
 #pragma unroll
-        for (int u = 0; u < 16; ++u) cur[u] = nxt[u];
-        if (qq + 1 <= q - 2)
-          load_coupling<R, FWD>(Lt, T, I, solve_block<R, FWD>(T, qq + 1), rc, part, nxt);
-        if (ok) ok = wait_flag(xflags + K, sync, status);
-        const double* xv = x + 64 * K + part * 16;
+        for (int u = 0; u < 16; ++u) {
+          c0[u] = n0[u];
+          c1[u] = n1[u];
+        }
+        // next pair's tiles in flight while this pair's solutions are polled
+        load_coupling<R, FWD>(Lt, T, I, solve_block<FWD>(T, k0 + 2 <= last ? k0 + 2 : last), rc, part, n0);
+        load_coupling<R, FWD>(Lt, T, I, solve_block<FWD>(T, k0 + 3 <= last ? k0 + 3 : last), rc, part, n1);
+        double x0[16], x1[16];
+        uint32_t spins = 0;
+        for (;;) {
+          bool miss = false;
 #pragma unroll
-        for (int u = 0; u < 16; ++u) acc = fma((double)cur[u], xv[u], acc);
+          for (int u = 0; u < 16; ++u) {
+            const uint64_t m0 = msg_get(xpub + 64 * K0 + part * 16 + u);
+            const uint64_t m1 = msg_get(xpub + 64 * K1 + part * 16 + u);
+            miss |= (m0 == kEmpty) | (m1 == kEmpty);
+            x0[u] = __longlong_as_double((long long)m0);
+            x1[u] = __longlong_as_double((long long)m1);
+          }
+          if (!__syncthreads_or(miss) || !live) break;
+          if (tid == 0) {
+            if (__hip_atomic_load(&sync->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+              live = false;
+            } else if (++spins > kSpinLimit) {
+              __hip_atomic_store(&sync->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              if (status) atomicOr(status, 2);
+              live = false;
+            }
+            sh[0] = live ? 1.0 : 0.0;
+          }
+          __syncthreads();
+          live = sh[0] != 0.0;
+          __syncthreads();
+          __builtin_amdgcn_s_sleep(2);
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) acc = fma((double)c0[u], x0[u], acc);
+        if (two) {
+#pragma unroll
+          for (int u = 0; u < 16; ++u) acc = fma((double)c1[u], x1[u], acc);
+        }
       }
       const double sum = reduce4(acc, sh);
-      if (tid < 64) part_sum[64 * I + tid] = sum;
-      publish(pflags + I);
-      __syncthreads();
+      if (tid < 64) msg_put(psum + 64 * I + tid, sum);
     }
   }
-  exit_and_reset(sync, flags, 2 * T);
+  trsv_exit(sync, psum, xpub, 64 * T, true);
 }
 
 // Refinement residual s = g - (H + mu I) d in FP64 from the FP32/FP64 column-major lower
@@ -1023,18 +1153,29 @@ hipError_t launch_cholesky(const R* Hc, int ld, int n_pad, const double* mu_dev,
 
 template <typename R>
 hipError_t launch_trsv(bool forward, const R* Lt, const R* Linv, int n_pad, const double* b,
-                       double* x, double* acc_out, double* part_sum, SyncArea* sync,
-                       uint32_t* flags, int32_t* status, const LMState* lm, int gate,
+                       double* x, double* acc_out, uint64_t* psum, uint64_t* xpub,
+                       SyncArea* sync, int32_t* status, const LMState* lm, int gate,
                        hipStream_t st) {
   const int T = n_pad / 64;
-  const int ntasks = 1 + (T > 2 ? T - 2 : 0);
-  const int grid = ntasks < 256 ? ntasks : 256;
+  const int ntasks = 1 + (T > kChainD ? T - kChainD : 0);
+  // at least two workgroups, so helpers exist beside the worker whatever the task count
+  const int grid = ntasks < 2 ? 2 : (ntasks < 256 ? ntasks : 256);
   if (forward)
     hipLaunchKernelGGL((k_trsv<R, true>), dim3(grid), dim3(kThreads), 0, st, Lt, Linv, T, b, x,
-                       acc_out, part_sum, sync, flags, status, lm, gate);
+                       acc_out, psum, xpub, sync, status, lm, gate);
   else
     hipLaunchKernelGGL((k_trsv<R, false>), dim3(grid), dim3(kThreads), 0, st, Lt, Linv, T, b, x,
-                       acc_out, part_sum, sync, flags, status, lm, gate);
+                       acc_out, psum, xpub, sync, status, lm, gate);
+  return hipGetLastError();
+}
+
+// Fill n 64-bit message slots with kEmpty (once, when the message arrays are created).
+__global__ void k_fill_empty(uint64_t* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = kEmpty;
+}
+hipError_t launch_fill_empty(uint64_t* p, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_empty, dim3((n + 255) / 256), dim3(256), 0, st, p, n);
   return hipGetLastError();
 }
 
@@ -1067,7 +1208,7 @@ hipError_t set_chol_smem_attr() {
                                          const double*, double*, R*, R*, R*, SyncArea*,        \
                                          uint32_t*, uint32_t*, int32_t*, hipStream_t, int);    \
   template hipError_t launch_trsv<R>(bool, const R*, const R*, int, const double*, double*,    \
-                                     double*, double*, SyncArea*, uint32_t*, int32_t*,         \
+                                     double*, uint64_t*, uint64_t*, SyncArea*, int32_t*,       \
                                      const LMState*, int, hipStream_t);                        \
   template hipError_t launch_refine_resid<R>(const R*, int, int, const double*, const double*, \
                                              const double*, double*, double*, double*, double*, \

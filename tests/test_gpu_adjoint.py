@@ -85,3 +85,10 @@ def test_autograd_and_lbfgs_reach_the_lm_cost(env):
     f_lm = rime.cost(Ro)
     assert all(b <= a * (1 + 1e-12) for a, b in zip(costs, costs[1:]))
     assert costs[-1] <= f_lm * (1 + 1e-6), (costs[-1], f_lm)
+    # the same with the diagonal (Jacobi) change of variables
+    scale = ag.jacobi_scaling(prob, x.detach())
+    assert scale.shape == x.shape and bool(torch.all(scale > 0))
+    Jp, costs_p = ag.lbfgs_calibrate(prob, x.detach(), n_iter=150, scaling=scale)
+    assert all(b <= a * (1 + 1e-12) for a, b in zip(costs_p, costs_p[1:]))
+    assert costs_p[-1] <= f_lm * (1 + 1e-6), (costs_p[-1], f_lm)
+    assert abs(ctx.residual(obs, ob.K, Vd, coh, Jp.contiguous(), 0, None) - costs_p[-1]) <= 1e-9 * costs_p[-1]

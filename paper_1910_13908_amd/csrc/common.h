@@ -133,7 +133,13 @@ hipError_t launch_cholesky(const R* Hc, int ld, int n_pad, const double* mu_dev,
                            const double* g, double* y, R* Lt, R* Linv, R* part, SyncArea* sync,
                            uint32_t* flags, uint32_t* yflags, int32_t* status, hipStream_t st,
                            int n_wg);
-// x = L^{-1} b (forward) or L^{-T} b (backward); acc_out (nullable) += x.  psum and xpub: 64 T
+// dst tile t = transpose of src tile t for ntiles packed 64x64 tiles (the backward solve reads
+// the transposed factor); skipped when lm reports a failed factorisation.
+template <typename R>
+hipError_t launch_transpose_tiles(const R* src, R* dst, int ntiles, const LMState* lm,
+                                  hipStream_t st);
+// x = L^{-1} b (forward: Lt, Linv) or L^{-T} b (backward: pass the transposed copies LtT,
+// LinvT); acc_out (nullable) += x.  psum and xpub: 64 T
 // message slots each, holding kEmpty before the launch (they hold it again after it).
 template <typename R>
 hipError_t launch_trsv(bool forward, const R* Lt, const R* Linv, int n_pad, const double* b,

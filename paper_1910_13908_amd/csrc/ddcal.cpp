@@ -222,7 +222,7 @@ ddc_status obs_dev(ddc_ctx* c, const ddc_obs* o, ObsDev& d) {
 // Buffers of one damped solve / LM solve in the workspace.
 struct SolveBufs {
   int n, n_pad, T, ld;
-  void *Hc, *Lt, *Linv, *part, *cpart;
+  void *Hc, *Lt, *Linv, *part, *cpart, *LtT, *LinvT;
   double *g, *diag, *d, *y, *s, *e, *cost_part, *s_part, *scalar, *prow, *pcol;
   size_t h_off;
 };
@@ -247,6 +247,8 @@ void layout_solve(Bump& bp, SolveBufs& b, int n, size_t es, int64_t B, int64_t n
   offs.push_back(bp.take(ntiles * 64 * sizeof(double)));               // prow
   offs.push_back(bp.take(ntiles * 64 * sizeof(double)));               // pcol
   offs.push_back(bp.take((size_t)b.T * 2 * 4096 * es));                 // Cholesky partial sums
+  offs.push_back(bp.take((size_t)b.T * (b.T + 1) / 2 * 4096 * es));    // LtT (transposed tiles)
+  offs.push_back(bp.take((size_t)b.T * 4096 * es));                    // LinvT
 }
 
 void bind_solve(ddc_ctx* c, SolveBufs& b, const std::vector<size_t>& o) {
@@ -267,6 +269,8 @@ void bind_solve(ddc_ctx* c, SolveBufs& b, const std::vector<size_t>& o) {
   b.prow = reinterpret_cast<double*>(w + o[13]);
   b.pcol = reinterpret_cast<double*>(w + o[14]);
   b.cpart = w + o[15];
+  b.LtT = w + o[16];
+  b.LinvT = w + o[17];
   b.h_off = o[0];
 }
 
@@ -293,15 +297,20 @@ ddc_status enqueue_solve(ddc_ctx* c, SolveBufs& b, LMState* lm, int refine_max, 
   R* Hc = reinterpret_cast<R*>(b.Hc);
   R* Lt = reinterpret_cast<R*>(b.Lt);
   R* Li = reinterpret_cast<R*>(b.Linv);
+  R* LtT = reinterpret_cast<R*>(b.LtT);
+  R* LiT = reinterpret_cast<R*>(b.LinvT);
   // the factorisation also runs the forward substitution y = L^{-1} g
   DDCCK(timed(c, T_CHOL, chol_flop(b.n), [&] {
     return launch_cholesky<R>(Hc, b.ld, b.n_pad, &lm->mu_eff, 0.0, b.g, b.y, Lt, Li,
                               reinterpret_cast<R*>(b.cpart), c->area(0), c->chol_flags(),
                               c->fwd_flags(), &lm->notpd, st, c->chol_wg);
   }));
+  // transposed copies of the factor and inverse tiles: the backward solves read them by rows
+  HIPCK(launch_transpose_tiles<R>(Lt, LtT, b.T * (b.T + 1) / 2, lm, st));
+  HIPCK(launch_transpose_tiles<R>(Li, LiT, b.T, lm, st));
   const double tri_bytes = (double)b.n_pad * (b.n_pad + 64) / 2 * sizeof(R);
   DDCCK(timed(c, T_TRSV, tri_bytes, [&] {
-    return launch_trsv<R>(false, Lt, Li, b.n_pad, b.y, b.d, nullptr, c->solve_psum(),
+    return launch_trsv<R>(false, LtT, LiT, b.n_pad, b.y, b.d, nullptr, c->solve_psum(),
                           c->solve_xpub(), c->area(2), &lm->timeout, lm, 1, st);
   }));
   for (int r = 0; r < refine_max; ++r) {
@@ -315,7 +324,7 @@ ddc_status enqueue_solve(ddc_ctx* c, SolveBufs& b, LMState* lm, int refine_max, 
                             c->solve_xpub(), c->area(1), &lm->timeout, lm, 2, st);
     }));
     DDCCK(timed(c, T_TRSV, tri_bytes, [&] {
-      return launch_trsv<R>(false, Lt, Li, b.n_pad, b.y, b.e, b.d, c->solve_psum(),
+      return launch_trsv<R>(false, LtT, LiT, b.n_pad, b.y, b.e, b.d, c->solve_psum(),
                             c->solve_xpub(), c->area(2), &lm->timeout, lm, 2, st);
     }));
   }

@@ -799,17 +799,21 @@ __device__ __forceinline__ double reduce4(double v, double* sh) {
 //   forward:  x_I = X_II (b_I - sum_{K<I} L_IK x_K),        blocks I = 0, 1, ..., T-1
 //   backward: x_I = X_II^T (b_I - sum_{K>I} L_KI^T x_K),    blocks I = T-1, ..., 0
 // Ticket 0 makes its workgroup the chain worker: it walks the blocks in solve order, applies
-// the kChainD-1 nearest blocks itself (their solutions in an LDS ring, the tiles that couple
-// them prefetched into registers one step ahead) and so never waits on another workgroup for
-// them.  The other workgroups (helpers, one per block from solve position kChainD on)
-// accumulate the contributions of all blocks at distance >= kChainD as their solutions
-// appear and hand the 64-entry partial sum to the worker, which has kChainD-1 steps of slack.
+// the D-1 nearest blocks itself (their solutions in an LDS ring, the tiles that couple them
+// prefetched into registers one step ahead) and so never waits on another workgroup for
+// them.  The other workgroups (helpers, one per block from solve position D on) accumulate
+// the contributions of all blocks at distance >= D as their solutions appear and hand the
+// 64-entry partial sum to the worker, which has D-1 steps of slack (D = chain_d<R> = 4: the
+// worker streams D tiles per step through its one compute unit).  In the worker the
+// four 16-column parts of a row sit in adjacent lanes of one wave, so a row sum is two
+// xor-shuffles in a fixed order and a step needs two workgroup barriers.
 // Hand-offs carry the data itself: solution blocks and partial sums travel through two
 // message arrays written and read with agent-scope relaxed 64-bit atomics, and a slot that
 // still holds kEmpty (a signalling-NaN payload that no arithmetic result carries) is not
 // ready yet.  So there is no fence or flag on the chain.  The worker fetches the partial sum
 // of the block two steps ahead.  The last workgroup out restores kEmpty in both arrays.
-constexpr int kChainD = 4;
+template <typename R>
+constexpr int chain_d() { return 4; }
 constexpr uint64_t kEmpty = 0x7FF4DD0000000001ull;
 
 __device__ __forceinline__ uint64_t msg_get(uint64_t* p) {
@@ -840,33 +844,46 @@ __device__ uint64_t msg_wait(uint64_t* p, SyncArea* sync, int32_t* status) {
 template <bool FWD>
 __device__ __forceinline__ int solve_block(int T, int q) { return FWD ? q : T - 1 - q; }
 
-// Tile coupling block I to block K (K before I in solve order), and the thread's 16 operands:
-// forward reads row r of L_IK, backward reads column c of L_KI.
-template <typename R, bool FWD>
-__device__ __forceinline__ void load_coupling(const R* __restrict__ Lt, int T, int I, int K,
-                                              int rc, int part, R (&v)[16]) {
-  if (FWD) {
-    const R* p = Lt + (int64_t)tile_index(I, K, T) * 4096 + rc * 64 + part * 16;
+// The thread's 16 operands of a tile row: 16 contiguous elements, fetched as 16-byte vectors.
+template <typename R>
+__device__ __forceinline__ void load16(const R* __restrict__ p, R (&v)[16]) {
+  if constexpr (sizeof(R) == 4) {
+    const f32x4* p4 = reinterpret_cast<const f32x4*>(p);
 #pragma unroll
-    for (int u = 0; u < 16; ++u) v[u] = p[u];
+    for (int j = 0; j < 4; ++j) {
+      const f32x4 t = p4[j];
+      v[4 * j] = t[0];
+      v[4 * j + 1] = t[1];
+      v[4 * j + 2] = t[2];
+      v[4 * j + 3] = t[3];
+    }
   } else {
-    const R* p = Lt + (int64_t)tile_index(K, I, T) * 4096 + (part * 16) * 64 + rc;
+    const f64x2* p2 = reinterpret_cast<const f64x2*>(p);
 #pragma unroll
-    for (int u = 0; u < 16; ++u) v[u] = p[u * 64];
+    for (int j = 0; j < 8; ++j) {
+      const f64x2 t = p2[j];
+      v[2 * j] = t[0];
+      v[2 * j + 1] = t[1];
+    }
   }
 }
 
+// Tile coupling block I to block K (K before I in solve order), row r, columns 16 part ..:
+// forward, row r of L_IK from the factor; backward, column r of L_KI, which is row r of the
+// transposed tile, from the transposed copy (L is then the transposed factor).
 template <typename R, bool FWD>
+__device__ __forceinline__ void load_coupling(const R* __restrict__ L, int T, int I, int K,
+                                              int rc, int part, R (&v)[16]) {
+  const int ti = FWD ? tile_index(I, K, T) : tile_index(K, I, T);
+  load16<R>(L + (int64_t)ti * 4096 + rc * 64 + part * 16, v);
+}
+
+// Row r, columns 16 part .. of X_II (forward) or of X_II^T (backward; Linv is then the
+// transposed copy of the inverses).
+template <typename R>
 __device__ __forceinline__ void load_inverse(const R* __restrict__ Linv, int I, int rc, int part,
                                              R (&v)[16]) {
-  const R* base = Linv + (int64_t)I * 4096;
-  if (FWD) {
-#pragma unroll
-    for (int u = 0; u < 16; ++u) v[u] = base[rc * 64 + part * 16 + u];
-  } else {
-#pragma unroll
-    for (int u = 0; u < 16; ++u) v[u] = base[(part * 16 + u) * 64 + rc];
-  }
+  load16<R>(Linv + (int64_t)I * 4096 + rc * 64 + part * 16, v);
 }
 
 // Leave the solve: the last workgroup out restores kEmpty in the message arrays (unless the
@@ -893,20 +910,24 @@ __device__ void trsv_exit(SyncArea* sync, uint64_t* psum, uint64_t* xpub, int n,
   }
 }
 
+// One wave per SIMD: the worker's prefetched tiles then have registers of their own, so no
+// register that a prefetch is still filling gets reused (which would stall the chain for a
+// full memory latency).
 template <typename R, bool FWD>
-__global__ __launch_bounds__(kThreads) void k_trsv(
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_trsv(
     const R* __restrict__ Lt, const R* __restrict__ Linv, int T, const double* __restrict__ b,
     double* __restrict__ x, double* __restrict__ acc_out, uint64_t* psum, uint64_t* xpub,
     SyncArea* sync, int32_t* status, const LMState* __restrict__ lm, int gate) {
   __shared__ double sh[kThreads];
   __shared__ double s_vec[64];
-  __shared__ double s_x[kChainD - 1][64];
+  constexpr int D = chain_d<R>();
+  __shared__ double s_x[D - 1][64];
   if (gated(lm, gate)) {
     trsv_exit(sync, psum, xpub, 64 * T, false);
     return;
   }
   const int tid = threadIdx.x, rc = tid & 63, part = tid >> 6;
-  const uint32_t ntasks = 1u + (uint32_t)(T > kChainD ? T - kChainD : 0);
+  const uint32_t ntasks = 1u + (uint32_t)(T > D ? T - D : 0);
   for (;;) {
     const uint32_t t = claim(sync);
     if (t >= ntasks) break;
@@ -919,55 +940,62 @@ __global__ __launch_bounds__(kThreads) void k_trsv(
       // The loop is unrolled by two with slots A and B for the scalars fetched ahead (the
       // right-hand side, the accumulation target and the partial-sum message), so no
       // fetched value is copied across the back-edge, which would also force the wait.
-      R inv[16], nb[kChainD - 1][16];
+      // Lane layout: row wr = 16 * wave + lane / 4, part wp = lane % 4.
+      const int wr = 16 * (tid >> 6) + ((tid & 63) >> 2), wp = tid & 3;
+      R inv[16], nb[D - 1][16];
       const double* ap = acc_out ? acc_out : b;
-      const int lt = tid & 63;
-      load_inverse<R, FWD>(Linv, solve_block<FWD>(T, 0), rc, part, inv);
-      double bA = b[64 * solve_block<FWD>(T, 0) + lt], bB = 0.0;
-      double aA = ap[64 * solve_block<FWD>(T, 0) + lt], aB = 0.0;
+      load_inverse<R>(Linv, solve_block<FWD>(T, 0), wr, wp, inv);
+      double bA = b[64 * solve_block<FWD>(T, 0) + wr], bB = 0.0;
+      double aA = ap[64 * solve_block<FWD>(T, 0) + wr], aB = 0.0;
       uint64_t mA = kEmpty, mB = kEmpty;
+      auto quad_sum = [](double v) {
+        // (p0 + p1) + (p2 + p3) in all four lanes of the quad, bitwise equal
+        v += __shfl_xor(v, 1);
+        return v + __shfl_xor(v, 2);
+      };
       auto step = [&](int q, uint64_t& m, double& b_use, double& b_fill, double& a_use,
                       double& a_fill) {
         const int I = solve_block<FWD>(T, q);
         double pv = 0.0;
-        if (q >= kChainD && tid < 64) {
+        if (q >= D) {
           uint64_t mm = m;
-          if (mm == kEmpty) mm = msg_wait(psum + 64 * I + tid, sync, status);
+          if (mm == kEmpty) mm = msg_wait(psum + 64 * I + wr, sync, status);
           pv = __longlong_as_double((long long)mm);
         }
-        // the message slot of position q is refilled with that of position q + 2
-        m = msg_get(psum + 64 * solve_block<FWD>(T, q + 2 < T ? q + 2 : T - 1) + lt);
         double a = 0.0;
 #pragma unroll
-        for (int d = 0; d < kChainD - 1; ++d) {
+        for (int d = 0; d < D - 1; ++d) {
           if (q - 1 - d >= 0) {
-            const double* xs = s_x[(q - 1 - d) % (kChainD - 1)] + part * 16;
+            const double* xs = s_x[(q - 1 - d) % (D - 1)] + wp * 16;
 #pragma unroll
             for (int u = 0; u < 16; ++u) a = fma((double)nb[d][u], xs[u], a);
           }
         }
-        const double asum = reduce4(a, sh);
-        if (tid < 64) s_vec[tid] = b_use - pv - asum;
+        const double sv = b_use - pv - quad_sum(a);
+        if (wp == 0) s_vec[wr] = sv;
         __syncthreads();
         double y = 0.0;
 #pragma unroll
-        for (int u = 0; u < 16; ++u) y = fma((double)inv[u], s_vec[part * 16 + u], y);
+        for (int u = 0; u < 16; ++u) y = fma((double)inv[u], s_vec[wp * 16 + u], y);
         {
           const int qn = q + 1 < T ? q + 1 : q;
           const int In = solve_block<FWD>(T, qn);
-          load_inverse<R, FWD>(Linv, In, rc, part, inv);
+          load_inverse<R>(Linv, In, wr, wp, inv);
 #pragma unroll
-          for (int d = 0; d < kChainD - 1; ++d)
-            load_coupling<R, FWD>(Lt, T, In, solve_block<FWD>(T, q - d >= 0 ? q - d : 0), rc, part, nb[d]);
-          b_fill = b[64 * In + lt];
-          a_fill = ap[64 * In + lt];
+          for (int d = 0; d < D - 1; ++d)
+            load_coupling<R, FWD>(Lt, T, In, solve_block<FWD>(T, q - d >= 0 ? q - d : 0), wr, wp, nb[d]);
+          b_fill = b[64 * In + wr];
+          a_fill = ap[64 * In + wr];
         }
-        const double xi = reduce4(y, sh);
-        if (tid < 64) {
-          x[64 * I + tid] = xi;
-          s_x[q % (kChainD - 1)][tid] = xi;
-          msg_put(xpub + 64 * I + tid, xi);
-          if (acc_out) acc_out[64 * I + tid] = a_use + xi;
+        // the message slot of position q is refilled with that of position q + 2, after the
+        // tile prefetches, so that it is the youngest load in flight
+        m = msg_get(psum + 64 * solve_block<FWD>(T, q + 2 < T ? q + 2 : T - 1) + wr);
+        const double xi = quad_sum(y);
+        if (wp == 0) {
+          x[64 * I + wr] = xi;
+          s_x[q % (D - 1)][wr] = xi;
+          msg_put(xpub + 64 * I + wr, xi);
+          if (acc_out) acc_out[64 * I + wr] = a_use + xi;
         }
         __syncthreads();
       };
@@ -976,11 +1004,11 @@ __global__ __launch_bounds__(kThreads) void k_trsv(
         if (q + 1 < T) step(q + 1, mB, bB, bA, aB, aA);
       }
     } else {
-      // helper for the block at solve position q = t + kChainD - 1: contributions of
-      // positions 0 .. q-kChainD, two solution blocks fetched per poll
-      const int q = (int)t + kChainD - 1;
+      // helper for the block at solve position q = t + D - 1: contributions of positions
+      // 0 .. q-D, two solution blocks fetched per poll
+      const int q = (int)t + D - 1;
       const int I = solve_block<FWD>(T, q);
-      const int last = q - kChainD;
+      const int last = q - D;
       R c0[16], c1[16], n0[16], n1[16];
       // unconditional prefetches with clamped positions, as in the worker
       load_coupling<R, FWD>(Lt, T, I, solve_block<FWD>(T, 0), rc, part, n0);
@@ -1135,6 +1163,30 @@ size_t chol_smem_bytes() {
   return 4 * 64 * Mfma<R>::STR * sizeof(R);
 }
 
+// Transpose every 64x64 tile of a packed array (ntiles tiles), one workgroup per tile through
+// LDS so that both the reads and the writes are coalesced.  Skipped after a failed
+// factorisation.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_transpose_tiles(const R* __restrict__ src,
+                                                              R* __restrict__ dst,
+                                                              const LMState* __restrict__ lm) {
+  __shared__ R t[64][65];
+  if (gated(lm, 1)) return;
+  const R* s = src + (int64_t)blockIdx.x * 4096;
+  R* d = dst + (int64_t)blockIdx.x * 4096;
+  for (int e = threadIdx.x; e < 4096; e += kThreads) t[e >> 6][e & 63] = s[e];
+  __syncthreads();
+  for (int e = threadIdx.x; e < 4096; e += kThreads) d[e] = t[e & 63][e >> 6];
+}
+
+template <typename R>
+hipError_t launch_transpose_tiles(const R* src, R* dst, int ntiles, const LMState* lm,
+                                  hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_transpose_tiles<R>, dim3(ntiles), dim3(kThreads), 0, st, src, dst, lm);
+  return hipGetLastError();
+}
+
 template <typename R>
 hipError_t launch_cholesky(const R* Hc, int ld, int n_pad, const double* mu_dev, double mu_host,
                            const double* g, double* y, R* Lt, R* Linv, R* part, SyncArea* sync,
@@ -1157,7 +1209,7 @@ hipError_t launch_trsv(bool forward, const R* Lt, const R* Linv, int n_pad, cons
                        SyncArea* sync, int32_t* status, const LMState* lm, int gate,
                        hipStream_t st) {
   const int T = n_pad / 64;
-  const int ntasks = 1 + (T > kChainD ? T - kChainD : 0);
+  const int ntasks = 1 + (T > chain_d<R>() ? T - chain_d<R>() : 0);
   // at least two workgroups, so helpers exist beside the worker whatever the task count
   const int grid = ntasks < 2 ? 2 : (ntasks < 256 ? ntasks : 256);
   if (forward)
@@ -1207,6 +1259,8 @@ hipError_t set_chol_smem_attr() {
   template hipError_t launch_cholesky<R>(const R*, int, int, const double*, double,             \
                                          const double*, double*, R*, R*, R*, SyncArea*,        \
                                          uint32_t*, uint32_t*, int32_t*, hipStream_t, int);    \
+  template hipError_t launch_transpose_tiles<R>(const R*, R*, int, const LMState*,              \
+                                                hipStream_t);                                  \
   template hipError_t launch_trsv<R>(bool, const R*, const R*, int, const double*, double*,    \
                                      double*, uint64_t*, uint64_t*, SyncArea*, int32_t*,       \
                                      const LMState*, int, hipStream_t);                        \

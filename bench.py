@@ -439,6 +439,23 @@ def main():
         "final_total_cost": final_cost,
     }
 
+    # station-factorised predict of the same sky (same coherencies; reported beside the
+    # direct predict, which the calibration step uses)
+    su, sv, sw = dd.device_station_uvw(ob)
+    coh_f = ctx.predict_factored(obs, su, sv, sw, sky, prec)
+    torch.cuda.synchronize()
+    del coh_f
+    ctx.enable_timing(True)
+    for _ in range(3):
+        coh_f = ctx.predict_factored(obs, su, sv, sw, sky, prec)
+        del coh_f
+    torch.cuda.synchronize()
+    n_pf, ms_pf, vis_pf = ctx.timing(dd.TIMER_PREDICT_FACTORED)
+    ctx.enable_timing(False)
+    out["predict_factored_gvis_per_s"] = vis_pf / (ms_pf * 1e-3) / 1e9 if ms_pf > 0 else 0.0
+    out["predict_factored_us"] = 1e3 * ms_pf / max(n_pf, 1)
+    torch.cuda.empty_cache()
+
     if prec == dd.MIXED and not args.no_fp64_compare:
         del V
         torch.cuda.empty_cache()

@@ -139,6 +139,21 @@ int64_t ddc_workspace_bytes(const ddc_ctx* ctx);
 ddc_status ddc_predict(ddc_ctx* ctx, const ddc_obs* obs, const ddc_sky* sky,
                        int32_t precision, void* coh);
 
+/* The same coherencies as ddc_predict, with station-factorised phasors: when the baseline
+ * coordinates are differences of station coordinates (uvw_pq = uvw_p - uvw_q, as for the
+ * canonical baselines), the phase splits as phi_pq = phi_p - phi_q and each cluster's
+ * coherency is the rank-S product C(p,q) = sum_s B_s E_p,s conj(E_q,s) with
+ * E_p,s = exp(-2 pi i phi_p,s) (measurement equation of ddc_predict; paper Section 2
+ * clusters, Section 3 baselines).  su, sv, sw: station coordinates in metres, DEVICE
+ * [T][N] FP64, caller-owned; obs supplies N, T, F and the frequencies (its baseline uvw are
+ * not read).  Phases are FP64, reduced to [-1/2, 1/2) turns per station; DDC_MIXED takes
+ * FP32 sin/cos and FP32 accumulation, DDC_FP64 stays in double.  The library holds
+ * T*F*S*ceil(N/64)*64 complex phasors of workspace.  Errors: DDC_EINVAL for NULL arrays,
+ * bad offsets or more than 65535 clusters. */
+ddc_status ddc_predict_factored(ddc_ctx* ctx, const ddc_obs* obs, const double* su,
+                                const double* sv, const double* sw, const ddc_sky* sky,
+                                int32_t precision, void* coh);
+
 /* res = vis - sum_{k<K} J_k C_k J_k^H and (optionally) cost = ||res||^2 accumulated in FP64.
  * vis, res: 8 planes [T][F][B]; coh: [K][8][T][F][B]; jones: [K][N][8].
  * res may be NULL (cost only); cost (HOST) may be NULL (no sync); res may alias vis. */
@@ -244,7 +259,8 @@ typedef enum {
   DDC_TIMER_TRIAL = 4,      /* trial cost; work = bytes */
   DDC_TIMER_MODEL = 5,      /* model add/subtract and residual; work = bytes */
   DDC_TIMER_REFINE = 6,     /* refinement residual; work = bytes */
-  DDC_TIMER_ADJOINT = 7     /* cost adjoint; work = bytes */
+  DDC_TIMER_ADJOINT = 7,    /* cost adjoint; work = bytes */
+  DDC_TIMER_PREDICT_FACTORED = 8  /* station-factorised predict; work = coherencies (K*T*F*B) */
 } ddc_timer;
 ddc_status ddc_enable_timing(ddc_ctx* ctx, int32_t on);
 ddc_status ddc_get_timing(ddc_ctx* ctx, int32_t which, int64_t* launches, double* total_ms,

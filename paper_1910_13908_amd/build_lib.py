@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libddcal.so")
-SOURCES = ["ddcal.cpp", "server.cpp", "k_predict.hip", "k_vis.hip", "k_chol.hip", "k_lm.hip"]
+SOURCES = ["ddcal.cpp", "server.cpp", "k_predict.hip", "k_predict_factored.hip", "k_vis.hip",
+           "k_chol.hip", "k_lm.hip"]
 ARCH = os.environ.get("DDC_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are kept out of the generated code.

@@ -93,6 +93,15 @@ inline int64_t predict_blocks(const PredictJob& j) {
 }
 
 // k_predict.hip
+// Station-factorised predict: phasors into `phasors` (phasor_bytes of scratch), then the
+// coherencies of all K clusters, same layout as launch_predict.
+size_t phasor_bytes(int N, int S, int T, int F, size_t es);
+template <typename R>
+hipError_t launch_predict_factored(const ObsDev& o, const double* su, const double* sv,
+                                   const double* sw, int K, int S, const int32_t* offs_dev,
+                                   const double* l, const double* m, const double* I,
+                                   const double* Q, const double* U, const double* V,
+                                   void* phasors, R* coh, hipStream_t st);
 template <typename R>
 hipError_t launch_predict_batch(const PredictJob* jobs_dev, int njobs, int64_t total_blocks,
                                 int grid, hipStream_t st);

@@ -20,7 +20,8 @@ namespace {
 constexpr int kMaxTiles = 512;                  // n_pad <= 32768 (N <= 4096 stations)
 constexpr size_t kSyncBytes = 2u << 20;        // [0, 1 MiB) zeroed; [1 MiB, 2 MiB) solve messages
 
-enum Timer { T_CHOL = 0, T_PREDICT, T_BUILD, T_TRSV, T_TRIAL, T_MODEL, T_REFINE, T_ADJOINT, T_COUNT };
+enum Timer { T_CHOL = 0, T_PREDICT, T_BUILD, T_TRSV, T_TRIAL, T_MODEL, T_REFINE, T_ADJOINT,
+             T_PREDICT_FACTORED, T_COUNT };
 
 struct TimerAcc {
   int64_t launches = 0;
@@ -486,6 +487,50 @@ ddc_status ddc_predict(ddc_ctx* c, const ddc_obs* obs, const ddc_sky* sky, int32
   return timed(c, T_PREDICT, terms, [&] {
     return launch_predict<double>(o, K, offs, sky->cluster_offset, sky->l, sky->m, sky->I, sky->Q,
                                   sky->U, sky->V, reinterpret_cast<double*>(coh), c->stream);
+  });
+}
+
+ddc_status ddc_predict_factored(ddc_ctx* c, const ddc_obs* obs, const double* su,
+                                const double* sv, const double* sw, const ddc_sky* sky,
+                                int32_t prec, void* coh) {
+  if (!c) return DDC_EINVAL;
+  (void)hipSetDevice(c->device);
+  ObsDev o;
+  DDCCK(obs_dev(c, obs, o));
+  DDCCK(check_prec(c, prec));
+  if (!su || !sv || !sw) return fail(c, DDC_EINVAL, "station coordinates must not be NULL");
+  if (!sky || !coh) return fail(c, DDC_EINVAL, "sky and coh must not be NULL");
+  const int K = sky->n_clusters;
+  if (K < 1 || K > 65535 || !sky->cluster_offset)
+    return fail(c, DDC_EINVAL, "n_clusters must be in 1..65535 with offsets");
+  if (sky->cluster_offset[0] != 0) return fail(c, DDC_EINVAL, "cluster_offset[0] must be 0");
+  for (int k = 0; k < K; ++k)
+    if (sky->cluster_offset[k + 1] < sky->cluster_offset[k])
+      return fail(c, DDC_EINVAL, "cluster_offset must be non-decreasing");
+  const int S = sky->cluster_offset[K];
+  if (S > 0 && (!sky->l || !sky->m || !sky->I || !sky->Q || !sky->U || !sky->V))
+    return fail(c, DDC_EINVAL, "sky arrays must not be NULL");
+  const size_t es = prec == DDC_MIXED ? sizeof(float) : sizeof(double);
+  Bump bp;
+  const size_t off = bp.take((size_t)(K + 1) * sizeof(int32_t));
+  const size_t off_e = bp.take(phasor_bytes(o.N, S, o.T, o.F, es));
+  DDCCK(ensure_ws(c, bp.off));
+  int32_t* offs = reinterpret_cast<int32_t*>(c->ws + off);
+  void* E = c->ws + off_e;
+  HIPCK(hipMemcpyAsync(offs, sky->cluster_offset, (K + 1) * sizeof(int32_t), hipMemcpyHostToDevice,
+                       c->stream));
+  HIPCK(hipStreamSynchronize(c->stream));
+  const double vis = (double)K * o.T * o.F * o.B;
+  if (prec == DDC_MIXED)
+    return timed(c, T_PREDICT_FACTORED, vis, [&] {
+      return launch_predict_factored<float>(o, su, sv, sw, K, S, offs, sky->l, sky->m, sky->I,
+                                            sky->Q, sky->U, sky->V, E,
+                                            reinterpret_cast<float*>(coh), c->stream);
+    });
+  return timed(c, T_PREDICT_FACTORED, vis, [&] {
+    return launch_predict_factored<double>(o, su, sv, sw, K, S, offs, sky->l, sky->m, sky->I,
+                                           sky->Q, sky->U, sky->V, E,
+                                           reinterpret_cast<double*>(coh), c->stream);
   });
 }
 

@@ -29,10 +29,10 @@ MIXED = 1
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOTPD, ENONFINITE, ETIMEOUT = 0, -1, -2, -3, -4, -5, -6
 (TIMER_CHOLESKY, TIMER_PREDICT, TIMER_BUILD, TIMER_TRSV, TIMER_TRIAL, TIMER_MODEL, TIMER_REFINE,
- TIMER_ADJOINT) = range(8)
+ TIMER_ADJOINT, TIMER_PREDICT_FACTORED) = range(9)
 
 EXPORTS = ("ddc_default_lm_opts", "ddc_create", "ddc_destroy", "ddc_set_stream", "ddc_last_error",
-           "ddc_workspace_bytes", "ddc_predict", "ddc_residual", "ddc_add_model",
+           "ddc_workspace_bytes", "ddc_predict", "ddc_predict_factored", "ddc_residual", "ddc_add_model",
            "ddc_build_normal_eq", "ddc_damped_solve", "ddc_lm_solve", "ddc_calibrate",
            "ddc_cost_gradient", "ddc_enable_timing", "ddc_get_timing", "ddc_calibrate_footprint",
            "ddc_server_create", "ddc_server_destroy", "ddc_server_submit", "ddc_server_wait",
@@ -82,6 +82,8 @@ _lib.ddc_last_error.restype = ct.c_char_p
 _lib.ddc_workspace_bytes.argtypes = [_vp]
 _lib.ddc_workspace_bytes.restype = ct.c_int64
 _lib.ddc_predict.argtypes = [_vp, ct.POINTER(Obs), ct.POINTER(Sky), ct.c_int32, _vp]
+_lib.ddc_predict_factored.argtypes = [_vp, ct.POINTER(Obs), _vp, _vp, _vp, ct.POINTER(Sky),
+                                      ct.c_int32, _vp]
 _lib.ddc_residual.argtypes = [_vp, ct.POINTER(Obs), ct.c_int32, _vp, _vp, _vp, ct.c_int32, _vp,
                               ct.POINTER(ct.c_double)]
 _lib.ddc_add_model.argtypes = [_vp, ct.POINTER(Obs), ct.c_int32, _vp, _vp, _vp, ct.c_double,
@@ -181,6 +183,21 @@ class Context:
             out = torch.empty((sky.K, 8, obs.T, obs.F, obs.B), dtype=dt, device=obs.u.device)
         self._bind()
         self._check(_lib.ddc_predict(self.h, ct.byref(obs.c), ct.byref(sky.c), precision, _ptr(out)))
+        return out
+
+    def predict_factored(self, obs: "DeviceObs", su, sv, sw, sky: "DeviceSky", precision: int,
+                         out=None):
+        """ddc_predict_factored: su, sv, sw are [T, N] float64 station coordinates (metres)."""
+        torch = self._torch
+        dt = torch.float32 if precision == MIXED else torch.float64
+        for a in (su, sv, sw):
+            if a.dtype != torch.float64 or not a.is_contiguous() or tuple(a.shape) != (obs.T, obs.N):
+                raise ValueError("station coordinates must be contiguous float64 [T, N]")
+        if out is None:
+            out = torch.empty((sky.K, 8, obs.T, obs.F, obs.B), dtype=dt, device=obs.u.device)
+        self._bind()
+        self._check(_lib.ddc_predict_factored(self.h, ct.byref(obs.c), _ptr(su), _ptr(sv), _ptr(sw),
+                                              ct.byref(sky.c), precision, _ptr(out)))
         return out
 
     def residual(self, obs, K, vis, coh, jones, precision, res=None, want_cost=True):
@@ -349,6 +366,13 @@ def device_obs(ob, device="cuda"):
     import torch
     t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=device)
     return DeviceObs(t(ob.u), t(ob.v), t(ob.w), t(ob.freqs), ob.N)
+
+
+def device_station_uvw(ob, device="cuda"):
+    """(su, sv, sw): station coordinates [T, N] float64 on the device, from a synth.Obs."""
+    import torch
+    return tuple(torch.as_tensor(np.ascontiguousarray(ob.suvw[..., i]), dtype=torch.float64,
+                                 device=device) for i in range(3))
 
 
 def device_sky(ob, device="cuda"):

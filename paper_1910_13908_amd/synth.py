@@ -104,6 +104,7 @@ class Obs:
     cluster_offset: np.ndarray  # [K+1] int32
     jones_true: np.ndarray     # [K, N, 2, 2] complex128
     noise: np.ndarray          # [T, F, B, 2, 2] complex128 (already scaled by sigma)
+    suvw: Optional[np.ndarray] = None   # [T, N, 3] station (u, v, w), metres; baseline = p - q
 
     @property
     def N(self) -> int:
@@ -222,7 +223,7 @@ def make_obs(cfg: ObsConfig, seed: int = 0, with_noise: bool = True) -> Obs:
                u=np.ascontiguousarray(buvw[..., 0]), v=np.ascontiguousarray(buvw[..., 1]),
                w=np.ascontiguousarray(buvw[..., 2]), freqs=np.asarray(cfg.freqs_hz, dtype=np.float64),
                l=l, m=m, I=I, Q=Q, U=U, V=V, cluster_offset=offs,
-               jones_true=np.ascontiguousarray(J), noise=noise)
+               jones_true=np.ascontiguousarray(J), noise=noise, suvw=np.ascontiguousarray(suvw))
 
 
 SERVE_N = (64, 128, 256, 384, 512)

@@ -101,7 +101,9 @@ def test_normal_equations(dd, ctx, prec, pol):
 
 
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
-@pytest.mark.parametrize("n", [8, 64, 100, 512, 1000])
+# n spans 1..16 tiles of 64: around the solves' chain distance of four blocks (T = 3, 4, 5
+# blocks: no helper, one helper, two helpers) and ragged last tiles
+@pytest.mark.parametrize("n", [8, 64, 100, 150, 250, 300, 512, 1000])
 def test_damped_solve(dd, ctx, prec, n):
     import torch
     rng = np.random.default_rng(n)

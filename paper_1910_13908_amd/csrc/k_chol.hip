@@ -29,6 +29,8 @@
 // residual g - (H + mu I) d are FP64.
 #include "common.h"
 
+#include <type_traits>
+
 namespace ddc {
 namespace {
 
@@ -814,6 +816,24 @@ __device__ __forceinline__ double reduce4(double v, double* sh) {
 // of the block two steps ahead.  The last workgroup out restores kEmpty in both arrays.
 template <typename R>
 constexpr int chain_d() { return 4; }
+// Register slots of the chain worker's operands (prefetch depth + 1): three in FP32, two in
+// FP64, where the operands take twice the registers.
+template <typename R>
+constexpr int trsv_slots() { return sizeof(R) == 4 ? 3 : 2; }
+
+// Lane exchange inside quads of lanes by DPP quad permutes (no LDS round trip).
+template <int CTRL>
+__device__ __forceinline__ double dpp_quad(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+// (p0 + p1) + (p2 + p3) of the four lanes of a quad, bitwise equal in all four.
+__device__ __forceinline__ double quad_sum(double v) {
+  v += dpp_quad<0xB1>(v);      // quad_perm [1,0,3,2]: partner lane ^ 1
+  return v + dpp_quad<0x4E>(v);  // quad_perm [2,3,0,1]: partner lane ^ 2
+}
 constexpr uint64_t kEmpty = 0x7FF4DD0000000001ull;
 
 __device__ __forceinline__ uint64_t msg_get(uint64_t* p) {
@@ -932,76 +952,89 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
     const uint32_t t = claim(sync);
     if (t >= ntasks) break;
     if (t == 0) {
-      // chain worker; inv, nb, bq and aq hold the operands of position q, fetched during
-      // step q-1; mq holds the partial-sum message of position q, mq1 that of q+1
-      // The prefetches are unconditional, with positions clamped into range (the values
-      // fetched for a position that does not exist are never used): a conditional load
-      // would make the wave wait for it at the join instead of at its use one step later.
-      // The loop is unrolled by two with slots A and B for the scalars fetched ahead (the
-      // right-hand side, the accumulation target and the partial-sum message), so no
-      // fetched value is copied across the back-edge, which would also force the wait.
+      // Chain worker.  Operands of a position (the row parts of X_II and of the D-1 coupling
+      // tiles, the right-hand side and the accumulation target) sit in one of NS register
+      // slots, filled PF = NS-1 steps ahead at the start of a step, so a tile fetch has PF
+      // whole steps to arrive.  The partial-sum message of a position is fetched two steps
+      // ahead, after that step's tile fetches, so it is the youngest load in flight when it
+      // is needed (the vector-memory counter is in order).  Fetches are unconditional with
+      // positions clamped into range (values fetched for a position that does not exist are
+      // never used): a conditional load would make the wave wait for it at the join.  The
+      // step loop is unrolled by NS, so every slot is a fixed set of registers.
       // Lane layout: row wr = 16 * wave + lane / 4, part wp = lane % 4.
+      constexpr int NS = trsv_slots<R>(), PF = NS - 1;
       const int wr = 16 * (tid >> 6) + ((tid & 63) >> 2), wp = tid & 3;
-      R inv[16], nb[D - 1][16];
+      R inv[NS][16], nb[NS][D - 1][16];
+      double bq[NS], aq[NS];
+      uint64_t mq[NS];
       const double* ap = acc_out ? acc_out : b;
-      load_inverse<R>(Linv, solve_block<FWD>(T, 0), wr, wp, inv);
-      double bA = b[64 * solve_block<FWD>(T, 0) + wr], bB = 0.0;
-      double aA = ap[64 * solve_block<FWD>(T, 0) + wr], aB = 0.0;
-      uint64_t mA = kEmpty, mB = kEmpty;
-      auto quad_sum = [](double v) {
-        // (p0 + p1) + (p2 + p3) in all four lanes of the quad, bitwise equal
-        v += __shfl_xor(v, 1);
-        return v + __shfl_xor(v, 2);
+      auto fetch = [&](auto slot, int p) {
+        constexpr int S = decltype(slot)::value;
+        const int pc = p < T ? p : T - 1;
+        const int In = solve_block<FWD>(T, pc);
+#pragma unroll
+        for (int d = 0; d < D - 1; ++d)
+          load_coupling<R, FWD>(Lt, T, In, solve_block<FWD>(T, pc - 1 - d >= 0 ? pc - 1 - d : 0),
+                                wr, wp, nb[S][d]);
+        load_inverse<R>(Linv, In, wr, wp, inv[S]);
+        bq[S] = b[64 * In + wr];
+        aq[S] = ap[64 * In + wr];
       };
-      auto step = [&](int q, uint64_t& m, double& b_use, double& b_fill, double& a_use,
-                      double& a_fill) {
+#pragma unroll
+      for (int s = 0; s < NS; ++s) mq[s] = kEmpty;
+      if constexpr (NS == 3) {
+        fetch(std::integral_constant<int, 0>{}, 0);
+        fetch(std::integral_constant<int, 1>{}, 1);
+      } else {
+        fetch(std::integral_constant<int, 0>{}, 0);
+      }
+      auto step = [&](auto slot, int q) {
+        constexpr int S = decltype(slot)::value;
+        fetch(std::integral_constant<int, (S + PF) % NS>{}, q + PF);
         const int I = solve_block<FWD>(T, q);
         double pv = 0.0;
         if (q >= D) {
-          uint64_t mm = m;
+          uint64_t mm = mq[S];
           if (mm == kEmpty) mm = msg_wait(psum + 64 * I + wr, sync, status);
           pv = __longlong_as_double((long long)mm);
         }
-        double a = 0.0;
+        // four independent chains keep the dependent-FMA latency off the step
+        double a4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int d = 0; d < D - 1; ++d) {
           if (q - 1 - d >= 0) {
             const double* xs = s_x[(q - 1 - d) % (D - 1)] + wp * 16;
 #pragma unroll
-            for (int u = 0; u < 16; ++u) a = fma((double)nb[d][u], xs[u], a);
+            for (int u = 0; u < 16; ++u) a4[u & 3] = fma((double)nb[S][d][u], xs[u], a4[u & 3]);
           }
         }
-        const double sv = b_use - pv - quad_sum(a);
+        const double sv = bq[S] - pv - quad_sum((a4[0] + a4[1]) + (a4[2] + a4[3]));
         if (wp == 0) s_vec[wr] = sv;
         __syncthreads();
-        double y = 0.0;
+        double y4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int u = 0; u < 16; ++u) y = fma((double)inv[u], s_vec[wp * 16 + u], y);
-        {
-          const int qn = q + 1 < T ? q + 1 : q;
-          const int In = solve_block<FWD>(T, qn);
-          load_inverse<R>(Linv, In, wr, wp, inv);
-#pragma unroll
-          for (int d = 0; d < D - 1; ++d)
-            load_coupling<R, FWD>(Lt, T, In, solve_block<FWD>(T, q - d >= 0 ? q - d : 0), wr, wp, nb[d]);
-          b_fill = b[64 * In + wr];
-          a_fill = ap[64 * In + wr];
-        }
-        // the message slot of position q is refilled with that of position q + 2, after the
-        // tile prefetches, so that it is the youngest load in flight
-        m = msg_get(psum + 64 * solve_block<FWD>(T, q + 2 < T ? q + 2 : T - 1) + wr);
-        const double xi = quad_sum(y);
+        for (int u = 0; u < 16; ++u) y4[u & 3] = fma((double)inv[S][u], s_vec[wp * 16 + u], y4[u & 3]);
+        mq[(S + 2) % NS] = msg_get(psum + 64 * solve_block<FWD>(T, q + 2 < T ? q + 2 : T - 1) + wr);
+        const double xi = quad_sum((y4[0] + y4[1]) + (y4[2] + y4[3]));
         if (wp == 0) {
           x[64 * I + wr] = xi;
           s_x[q % (D - 1)][wr] = xi;
           msg_put(xpub + 64 * I + wr, xi);
-          if (acc_out) acc_out[64 * I + wr] = a_use + xi;
+          if (acc_out) acc_out[64 * I + wr] = aq[S] + xi;
         }
         __syncthreads();
       };
-      for (int q = 0; q < T; q += 2) {
-        step(q, mA, bA, bB, aA, aB);
-        if (q + 1 < T) step(q + 1, mB, bB, bA, aB, aA);
+      // whole groups of NS steps in the loop (no conditional step inside it, so no path
+      // reaches the back-edge with a slot's fetch unconsumed), the remainder after it
+      int q = 0;
+      for (; q + NS <= T; q += NS) {
+        step(std::integral_constant<int, 0>{}, q);
+        step(std::integral_constant<int, 1>{}, q + 1);
+        if constexpr (NS == 3) step(std::integral_constant<int, 2 % NS>{}, q + 2);
+      }
+      if (q < T) step(std::integral_constant<int, 0>{}, q);
+      if constexpr (NS == 3) {
+        if (q + 1 < T) step(std::integral_constant<int, 1>{}, q + 1);
       }
     } else {
       // helper for the block at solve position q = t + D - 1: contributions of positions

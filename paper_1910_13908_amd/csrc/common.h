@@ -142,11 +142,12 @@ hipError_t launch_cholesky(const R* Hc, int ld, int n_pad, const double* mu_dev,
                            const double* g, double* y, R* Lt, R* Linv, R* part, SyncArea* sync,
                            uint32_t* flags, uint32_t* yflags, int32_t* status, hipStream_t st,
                            int n_wg);
-// dst tile t = transpose of src tile t for ntiles packed 64x64 tiles (the backward solve reads
-// the transposed factor); skipped when lm reports a failed factorisation.
+// dst tile t = transpose of src tile t for ntiles packed 64x64 tiles, and likewise dst2/src2
+// for ntiles2 tiles, in one launch (the backward solve reads the transposed factor and
+// inverses); skipped when lm reports a failed factorisation.
 template <typename R>
-hipError_t launch_transpose_tiles(const R* src, R* dst, int ntiles, const LMState* lm,
-                                  hipStream_t st);
+hipError_t launch_transpose_tiles(const R* src, R* dst, int ntiles, const R* src2, R* dst2,
+                                  int ntiles2, const LMState* lm, hipStream_t st);
 // x = L^{-1} b (forward: Lt, Linv) or L^{-T} b (backward: pass the transposed copies LtT,
 // LinvT); acc_out (nullable) += x.  psum and xpub: 64 T
 // message slots each, holding kEmpty before the launch (they hold it again after it).
@@ -157,12 +158,14 @@ hipError_t launch_trsv(bool forward, const R* Lt, const R* Linv, int n_pad, cons
                        hipStream_t st);
 // Fill n message slots with kEmpty.
 hipError_t launch_fill_empty(uint64_t* p, int n, hipStream_t st);
-// s = g - (H + mu I) d (FP64) via per-tile partials prow/pcol ([T(T+1)/2][64] each).
+// s = g - (H + mu I) d (FP64) via per-tile partials prow/pcol ([T(T+1)/2][64] each); the
+// same launch closes the refinement step (refine_done once ||s||^2 <= tol2 ||g||^2, else
+// refine_steps + 1), with sync->exited as its zeroed counter.
 template <typename R>
 hipError_t launch_refine_resid(const R* Hc, int ld, int n_pad, const double* mu_dev,
                                const double* g, const double* d, double* s, double* s_part,
-                               double* prow, double* pcol, const LMState* lm, int gate,
-                               hipStream_t st);
+                               double* prow, double* pcol, LMState* lm, int gate,
+                               SyncArea* sync, double tol2, hipStream_t st);
 hipError_t set_chol_smem_attr();
 
 // k_lm.hip
@@ -172,8 +175,6 @@ hipError_t launch_lm_pre(LMState* st, const double* cost_part, int nblk, const d
                          hipStream_t s);
 hipError_t launch_lm_post(LMState* st, const double* cost_part, int nblk, const double* d,
                           const double* g, int n8, double* jones, hipStream_t s);
-hipError_t launch_refine_ctrl(LMState* st, const double* s_part, int T, double tol2,
-                              hipStream_t s);
 hipError_t launch_solve_setup(LMState* st, const double* g, int n, double mu, int refine_max,
                               hipStream_t s);
 hipError_t launch_copy_state(const LMState* st, LMState* dst, hipStream_t s);

@@ -307,8 +307,7 @@ ddc_status enqueue_solve(ddc_ctx* c, SolveBufs& b, LMState* lm, int refine_max, 
                               c->fwd_flags(), &lm->notpd, st, c->chol_wg);
   }));
   // transposed copies of the factor and inverse tiles: the backward solves read them by rows
-  HIPCK(launch_transpose_tiles<R>(Lt, LtT, b.T * (b.T + 1) / 2, lm, st));
-  HIPCK(launch_transpose_tiles<R>(Li, LiT, b.T, lm, st));
+  HIPCK(launch_transpose_tiles<R>(Lt, LtT, b.T * (b.T + 1) / 2, Li, LiT, b.T, lm, st));
   const double tri_bytes = (double)b.n_pad * (b.n_pad + 64) / 2 * sizeof(R);
   DDCCK(timed(c, T_TRSV, tri_bytes, [&] {
     return launch_trsv<R>(false, LtT, LiT, b.n_pad, b.y, b.d, nullptr, c->solve_psum(),
@@ -317,9 +316,8 @@ ddc_status enqueue_solve(ddc_ctx* c, SolveBufs& b, LMState* lm, int refine_max, 
   for (int r = 0; r < refine_max; ++r) {
     DDCCK(timed(c, T_REFINE, (double)b.n_pad * b.n_pad * sizeof(R), [&] {
       return launch_refine_resid<R>(Hc, b.ld, b.n_pad, &lm->mu_eff, b.g, b.d, b.s, b.s_part,
-                                    b.prow, b.pcol, lm, 2, st);
+                                    b.prow, b.pcol, lm, 2, c->area(3), tol * tol, st);
     }));
-    HIPCK(launch_refine_ctrl(lm, b.s_part, b.T, tol * tol, st));
     DDCCK(timed(c, T_TRSV, tri_bytes, [&] {
       return launch_trsv<R>(true, Lt, Li, b.n_pad, b.s, b.y, nullptr, c->solve_psum(),
                             c->solve_xpub(), c->area(1), &lm->timeout, lm, 2, st);

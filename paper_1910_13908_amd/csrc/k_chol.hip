@@ -906,20 +906,18 @@ __device__ __forceinline__ void load_inverse(const R* __restrict__ Linv, int I, 
   load16<R>(Linv + (int64_t)I * 4096 + rc * 64 + part * 16, v);
 }
 
-// Leave the solve: the last workgroup out restores kEmpty in the message arrays (unless the
-// launch was gated and wrote none) and clears the counters.
-__device__ void trsv_exit(SyncArea* sync, uint64_t* psum, uint64_t* xpub, int n, bool dirty) {
+// Leave the solve: the last workgroup out restores kEmpty in the message arrays and clears
+// the counters.
+__device__ void trsv_exit(SyncArea* sync, uint64_t* psum, uint64_t* xpub, int n) {
   __shared__ int s_last;
   __threadfence();      // this workgroup's message stores land before it is counted out
   __syncthreads();
   if (threadIdx.x == 0) s_last = (atomicAdd(&sync->exited, 1u) == gridDim.x - 1);
   __syncthreads();
   if (s_last) {
-    if (dirty) {
-      for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        __hip_atomic_store(psum + i, kEmpty, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(xpub + i, kEmpty, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      __hip_atomic_store(psum + i, kEmpty, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(xpub + i, kEmpty, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (threadIdx.x == 0) {
       sync->ticket = 0u;
@@ -942,10 +940,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
   __shared__ double s_vec[64];
   constexpr int D = chain_d<R>();
   __shared__ double s_x[D - 1][64];
-  if (gated(lm, gate)) {
-    trsv_exit(sync, psum, xpub, 64 * T, false);
-    return;
-  }
+  // a gated launch touches nothing (counters and message slots stay as the last solve left
+  // them), so its workgroups just leave
+  if (gated(lm, gate)) return;
   const int tid = threadIdx.x, rc = tid & 63, part = tid >> 6;
   const uint32_t ntasks = 1u + (uint32_t)(T > D ? T - D : 0);
   for (;;) {
@@ -1098,7 +1095,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
       if (tid < 64) msg_put(psum + 64 * I + tid, sum);
     }
   }
-  trsv_exit(sync, psum, xpub, 64 * T, true);
+  trsv_exit(sync, psum, xpub, 64 * T);
 }
 
 // Refinement residual s = g - (H + mu I) d in FP64 from the FP32/FP64 column-major lower
@@ -1158,12 +1155,14 @@ __global__ __launch_bounds__(kThreads) void k_symv_tiles(
   }
 }
 
+// The last block row to finish also closes the refinement step: ||s||^2 (a fixed-order sum of
+// the per-row partials) against tol^2 ||g||^2 sets refine_done, else counts a step.
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_symv_combine(
     int T, const double* __restrict__ mu_dev, const double* __restrict__ g,
     const double* __restrict__ d, const double* __restrict__ prow,
     const double* __restrict__ pcol, double* __restrict__ s, double* __restrict__ s_part,
-    const LMState* __restrict__ lm, int gate) {
+    LMState* lm, int gate, SyncArea* sync, double tol2) {
   if (gated(lm, gate)) return;
   __shared__ double sh[kThreads];
   const int B = blockIdx.x;           // block row
@@ -1187,6 +1186,26 @@ __global__ __launch_bounds__(kThreads) void k_symv_combine(
     for (int off = 32; off > 0; off >>= 1) sq += __shfl_down(sq, off, 64);
     if (tid == 0) s_part[B] = sq;
   }
+  __shared__ int s_last;
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) s_last = atomicAdd(&sync->exited, 1u) == gridDim.x - 1;
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  double v = 0.0;
+  for (int i = tid; i < T; i += kThreads) v += s_part[i];
+  sh[tid] = v;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if (tid < w) sh[tid] += sh[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (sh[0] <= tol2 * lm->g_norm2) lm->refine_done = 1;
+    else lm->refine_steps += 1;
+    sync->exited = 0u;
+  }
 }
 
 }  // namespace
@@ -1201,22 +1220,28 @@ size_t chol_smem_bytes() {
 // factorisation.
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_transpose_tiles(const R* __restrict__ src,
-                                                              R* __restrict__ dst,
+                                                              R* __restrict__ dst, int n1,
+                                                              const R* __restrict__ src2,
+                                                              R* __restrict__ dst2,
                                                               const LMState* __restrict__ lm) {
   __shared__ R t[64][65];
   if (gated(lm, 1)) return;
-  const R* s = src + (int64_t)blockIdx.x * 4096;
-  R* d = dst + (int64_t)blockIdx.x * 4096;
+  // blocks [0, n1) transpose tiles of the first array, the rest those of the second
+  const bool first = (int)blockIdx.x < n1;
+  const int64_t k = first ? blockIdx.x : blockIdx.x - n1;
+  const R* s = (first ? src : src2) + k * 4096;
+  R* d = (first ? dst : dst2) + k * 4096;
   for (int e = threadIdx.x; e < 4096; e += kThreads) t[e >> 6][e & 63] = s[e];
   __syncthreads();
   for (int e = threadIdx.x; e < 4096; e += kThreads) d[e] = t[e & 63][e >> 6];
 }
 
 template <typename R>
-hipError_t launch_transpose_tiles(const R* src, R* dst, int ntiles, const LMState* lm,
-                                  hipStream_t st) {
-  if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_transpose_tiles<R>, dim3(ntiles), dim3(kThreads), 0, st, src, dst, lm);
+hipError_t launch_transpose_tiles(const R* src, R* dst, int ntiles, const R* src2, R* dst2,
+                                  int ntiles2, const LMState* lm, hipStream_t st) {
+  if (ntiles + ntiles2 <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_transpose_tiles<R>, dim3(ntiles + ntiles2), dim3(kThreads), 0, st, src,
+                     dst, ntiles, src2, dst2, lm);
   return hipGetLastError();
 }
 
@@ -1267,14 +1292,14 @@ hipError_t launch_fill_empty(uint64_t* p, int n, hipStream_t st) {
 template <typename R>
 hipError_t launch_refine_resid(const R* Hc, int ld, int n_pad, const double* mu_dev,
                                const double* g, const double* d, double* s, double* s_part,
-                               double* prow, double* pcol, const LMState* lm, int gate,
-                               hipStream_t st) {
+                               double* prow, double* pcol, LMState* lm, int gate,
+                               SyncArea* sync, double tol2, hipStream_t st) {
   const int T = n_pad / 64;
   const int ntiles = T * (T + 1) / 2;
   hipLaunchKernelGGL(k_symv_tiles<R>, dim3(ntiles), dim3(kThreads), 0, st, Hc, (int64_t)ld, T, d,
                      prow, pcol, lm, gate);
   hipLaunchKernelGGL(k_symv_combine<R>, dim3(T), dim3(kThreads), 0, st, T, mu_dev, g, d, prow,
-                     pcol, s, s_part, lm, gate);
+                     pcol, s, s_part, lm, gate, sync, tol2);
   return hipGetLastError();
 }
 
@@ -1292,14 +1317,14 @@ hipError_t set_chol_smem_attr() {
   template hipError_t launch_cholesky<R>(const R*, int, int, const double*, double,             \
                                          const double*, double*, R*, R*, R*, SyncArea*,        \
                                          uint32_t*, uint32_t*, int32_t*, hipStream_t, int);    \
-  template hipError_t launch_transpose_tiles<R>(const R*, R*, int, const LMState*,              \
-                                                hipStream_t);                                  \
+  template hipError_t launch_transpose_tiles<R>(const R*, R*, int, const R*, R*, int,           \
+                                                const LMState*, hipStream_t);                  \
   template hipError_t launch_trsv<R>(bool, const R*, const R*, int, const double*, double*,    \
                                      double*, uint64_t*, uint64_t*, SyncArea*, int32_t*,       \
                                      const LMState*, int, hipStream_t);                        \
   template hipError_t launch_refine_resid<R>(const R*, int, int, const double*, const double*, \
                                              const double*, double*, double*, double*, double*, \
-                                             const LMState*, int, hipStream_t);
+                                             LMState*, int, SyncArea*, double, hipStream_t);
 DDC_INST(float)
 DDC_INST(double)
 #undef DDC_INST

@@ -141,17 +141,6 @@ __global__ __launch_bounds__(kThreads) void k_lm_post(LMState* st, const double*
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_refine_ctrl(LMState* st, const double* s_part,
-                                                          int T, double tol2) {
-  __shared__ double sh[kThreads];
-  if (st->notpd || st->refine_done) return;
-  const double r2 = fixed_sum(s_part, T, sh);
-  if (threadIdx.x == 0) {
-    if (r2 <= tol2 * st->g_norm2) st->refine_done = 1;
-    else st->refine_steps += 1;
-  }
-}
-
 // Stand-alone damped solve: mu_eff = mu, ||g||^2, refinement bookkeeping.
 __global__ __launch_bounds__(kThreads) void k_solve_setup(LMState* st, const double* g, int n,
                                                           double mu, int refine_max) {
@@ -218,11 +207,6 @@ hipError_t launch_lm_post(LMState* st, const double* cost_part, int nblk, const 
                           const double* g, int n8, double* jones, hipStream_t s) {
   hipLaunchKernelGGL(k_lm_post, dim3(1), dim3(kThreads), 0, s, st, cost_part, nblk, d, g, n8,
                      jones);
-  return hipGetLastError();
-}
-hipError_t launch_refine_ctrl(LMState* st, const double* s_part, int T, double tol2,
-                              hipStream_t s) {
-  hipLaunchKernelGGL(k_refine_ctrl, dim3(1), dim3(kThreads), 0, s, st, s_part, T, tol2);
   return hipGetLastError();
 }
 hipError_t launch_solve_setup(LMState* st, const double* g, int n, double mu, int refine_max,

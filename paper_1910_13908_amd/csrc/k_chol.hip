@@ -800,20 +800,24 @@ __device__ __forceinline__ double reduce4(double v, double* sh) {
 // factor, with the inverses X_II of the diagonal tiles:
 //   forward:  x_I = X_II (b_I - sum_{K<I} L_IK x_K),        blocks I = 0, 1, ..., T-1
 //   backward: x_I = X_II^T (b_I - sum_{K>I} L_KI^T x_K),    blocks I = T-1, ..., 0
-// Ticket 0 makes its workgroup the chain worker: it walks the blocks in solve order, applies
-// the D-1 nearest blocks itself (their solutions in an LDS ring, the tiles that couple them
-// prefetched into registers one step ahead) and so never waits on another workgroup for
-// them.  The other workgroups (helpers, one per block from solve position D on) accumulate
-// the contributions of all blocks at distance >= D as their solutions appear and hand the
-// 64-entry partial sum to the worker, which has D-1 steps of slack (D = chain_d<R> = 4: the
-// worker streams D tiles per step through its one compute unit).  In the worker the
-// four 16-column parts of a row sit in adjacent lanes of one wave, so a row sum is two
-// xor-shuffles in a fixed order and a step needs two workgroup barriers.
+// Ticket 0 makes its workgroup the chain worker: it walks the blocks in solve order and
+// applies the D-1 nearest blocks itself, so it never waits on another workgroup for them.  It
+// applies them by columns: in step q it reads x of the previous block once from LDS and adds
+// its products with the D-1 tiles below it into per-lane partial sums of the next D-1 blocks,
+// the first of which is then complete.  The other workgroups (helpers, one per block from
+// solve position D on) accumulate the contributions of all blocks at distance >= D as their
+// solutions appear and hand the 64-entry partial sum to the worker, which has D-1 steps of
+// slack (D = chain_d<R> = 4: the worker streams D tiles per step through its one compute
+// unit, so a larger D slows every step).  In the worker the four 16-column parts of a row sit
+// in adjacent lanes of one wave, so a row sum is two DPP exchanges in a fixed order and a
+// step needs two workgroup barriers.
 // Hand-offs carry the data itself: solution blocks and partial sums travel through two
 // message arrays written and read with agent-scope relaxed 64-bit atomics, and a slot that
 // still holds kEmpty (a signalling-NaN payload that no arithmetic result carries) is not
 // ready yet.  So there is no fence or flag on the chain.  The worker fetches the partial sum
-// of the block two steps ahead.  The last workgroup out restores kEmpty in both arrays.
+// of the block two steps ahead; a helper watches one entry with one lane before fetching
+// whole blocks, which keeps the polling off the lines the worker writes.  The last workgroup
+// out restores kEmpty in both arrays.
 template <typename R>
 constexpr int chain_d() { return 4; }
 // Register slots of the chain worker's operands (prefetch depth + 1): three in FP32, two in
@@ -939,7 +943,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
   __shared__ double sh[kThreads];
   __shared__ double s_vec[64];
   constexpr int D = chain_d<R>();
-  __shared__ double s_x[D - 1][64];
+  __shared__ double s_y[2][64];   // the last two solution blocks
   // a gated launch touches nothing (counters and message slots stay as the last solve left
   // them), so its workgroups just leave
   if (gated(lm, gate)) return;
@@ -962,17 +966,22 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
       constexpr int NS = trsv_slots<R>(), PF = NS - 1;
       const int wr = 16 * (tid >> 6) + ((tid & 63) >> 2), wp = tid & 3;
       R inv[NS][16], nb[NS][D - 1][16];
+      double cacc[D - 1];
+#pragma unroll
+      for (int d = 0; d < D - 1; ++d) cacc[d] = 0.0;
       double bq[NS], aq[NS];
       uint64_t mq[NS];
       const double* ap = acc_out ? acc_out : b;
+      // step p applies y_{p-1} to blocks p .. p+D-2: the column tiles C(p+j, p-1)
       auto fetch = [&](auto slot, int p) {
         constexpr int S = decltype(slot)::value;
         const int pc = p < T ? p : T - 1;
         const int In = solve_block<FWD>(T, pc);
+        const int pk = pc >= 1 ? pc - 1 : 0;
 #pragma unroll
         for (int d = 0; d < D - 1; ++d)
-          load_coupling<R, FWD>(Lt, T, In, solve_block<FWD>(T, pc - 1 - d >= 0 ? pc - 1 - d : 0),
-                                wr, wp, nb[S][d]);
+          load_coupling<R, FWD>(Lt, T, solve_block<FWD>(T, pc + d < T ? pc + d : T - 1),
+                                solve_block<FWD>(T, pk), wr, wp, nb[S][d]);
         load_inverse<R>(Linv, In, wr, wp, inv[S]);
         bq[S] = b[64 * In + wr];
         aq[S] = ap[64 * In + wr];
@@ -995,17 +1004,22 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
           if (mm == kEmpty) mm = msg_wait(psum + 64 * I + wr, sync, status);
           pv = __longlong_as_double((long long)mm);
         }
-        // four independent chains keep the dependent-FMA latency off the step
-        double a4[4] = {0.0, 0.0, 0.0, 0.0};
+        // y_{q-1}, read once, goes into the per-lane partial sums of blocks q .. q+D-2; the
+        // first of them is then complete
+        if (q >= 1) {
+          const double* ys = s_y[(q - 1) & 1] + wp * 16;
 #pragma unroll
-        for (int d = 0; d < D - 1; ++d) {
-          if (q - 1 - d >= 0) {
-            const double* xs = s_x[(q - 1 - d) % (D - 1)] + wp * 16;
+          for (int d = 0; d < D - 1; ++d) {
+            double c2[2] = {0.0, 0.0};
 #pragma unroll
-            for (int u = 0; u < 16; ++u) a4[u & 3] = fma((double)nb[S][d][u], xs[u], a4[u & 3]);
+            for (int u = 0; u < 16; ++u) c2[u & 1] = fma((double)nb[S][d][u], ys[u], c2[u & 1]);
+            cacc[d] += c2[0] + c2[1];
           }
         }
-        const double sv = bq[S] - pv - quad_sum((a4[0] + a4[1]) + (a4[2] + a4[3]));
+        const double sv = bq[S] - pv - quad_sum(cacc[0]);
+#pragma unroll
+        for (int d = 0; d + 1 < D - 1; ++d) cacc[d] = cacc[d + 1];
+        cacc[D - 2] = 0.0;
         if (wp == 0) s_vec[wr] = sv;
         __syncthreads();
         double y4[4] = {0.0, 0.0, 0.0, 0.0};
@@ -1015,7 +1029,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
         const double xi = quad_sum((y4[0] + y4[1]) + (y4[2] + y4[3]));
         if (wp == 0) {
           x[64 * I + wr] = xi;
-          s_x[q % (D - 1)][wr] = xi;
+          s_y[q & 1][wr] = xi;
           msg_put(xpub + 64 * I + wr, xi);
           if (acc_out) acc_out[64 * I + wr] = aq[S] + xi;
         }
@@ -1059,6 +1073,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
         double x0[16], x1[16];
         uint32_t spins = 0;
         for (;;) {
+          // one lane watches the last entry of the newer block (a short bounded poll), so the
+          // helpers do not all keep re-reading the lines the worker is writing; every entry is
+          // then fetched and checked, as the entries need not appear in order
+          if (tid == 0) {
+            for (int sp = 0; sp < 4096 && msg_get(xpub + 64 * K1 + 63) == kEmpty; ++sp)
+              __builtin_amdgcn_s_sleep(2);
+          }
+          __syncthreads();
           bool miss = false;
 #pragma unroll
           for (int u = 0; u < 16; ++u) {

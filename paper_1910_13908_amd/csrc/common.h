@@ -160,10 +160,11 @@ hipError_t launch_trsv(bool forward, const R* Lt, const R* Linv, int n_pad, cons
 hipError_t launch_fill_empty(uint64_t* p, int n, hipStream_t st);
 // s = g - (H + mu I) d (FP64) via per-tile partials prow/pcol ([T(T+1)/2][64] each); the
 // same launch closes the refinement step (refine_done once ||s||^2 <= tol2 ||g||^2, else
-// refine_steps + 1), with sync->exited as its zeroed counter.
+// refine_steps + 1), with sync->exited as its zeroed counter and T message slots in norms
+// that hold kEmpty before the launch (and again after it).
 template <typename R>
 hipError_t launch_refine_resid(const R* Hc, int ld, int n_pad, const double* mu_dev,
-                               const double* g, const double* d, double* s, double* s_part,
+                               const double* g, const double* d, double* s, uint64_t* norms,
                                double* prow, double* pcol, LMState* lm, int gate,
                                SyncArea* sync, double tol2, hipStream_t st);
 hipError_t set_chol_smem_attr();

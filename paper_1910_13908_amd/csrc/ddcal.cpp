@@ -65,6 +65,7 @@ struct ddc_ctx {
   // triangular-solve message arrays (partial sums, solution blocks), kEmpty between solves
   uint64_t* solve_psum() { return reinterpret_cast<uint64_t*>(sync + (1u << 20)); }
   uint64_t* solve_xpub() { return solve_psum() + 64 * kMaxTiles; }
+  uint64_t* refine_norms() { return solve_xpub() + 64 * kMaxTiles; }
 };
 
 namespace {
@@ -315,8 +316,9 @@ ddc_status enqueue_solve(ddc_ctx* c, SolveBufs& b, LMState* lm, int refine_max, 
   }));
   for (int r = 0; r < refine_max; ++r) {
     DDCCK(timed(c, T_REFINE, (double)b.n_pad * b.n_pad * sizeof(R), [&] {
-      return launch_refine_resid<R>(Hc, b.ld, b.n_pad, &lm->mu_eff, b.g, b.d, b.s, b.s_part,
-                                    b.prow, b.pcol, lm, 2, c->area(3), tol * tol, st);
+      return launch_refine_resid<R>(Hc, b.ld, b.n_pad, &lm->mu_eff, b.g, b.d, b.s,
+                                    c->refine_norms(), b.prow, b.pcol, lm, 2, c->area(3),
+                                    tol * tol, st);
     }));
     DDCCK(timed(c, T_TRSV, tri_bytes, [&] {
       return launch_trsv<R>(true, Lt, Li, b.n_pad, b.s, b.y, nullptr, c->solve_psum(),
@@ -413,7 +415,7 @@ ddc_status ddc_create(ddc_ctx** out, int32_t device) {
   c->device = device;
   if (hipMalloc(&c->sync, kSyncBytes) != hipSuccess ||
       hipMemset(c->sync, 0, 1u << 20) != hipSuccess ||
-      launch_fill_empty(c->solve_psum(), 2 * 64 * kMaxTiles, nullptr) != hipSuccess ||
+      launch_fill_empty(c->solve_psum(), 2 * 64 * kMaxTiles + kMaxTiles, nullptr) != hipSuccess ||
       set_chol_smem_attr() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
     (void)hipGetLastError();
     if (c->sync) (void)hipFree(c->sync);

@@ -1177,14 +1177,16 @@ __global__ __launch_bounds__(kThreads) void k_symv_tiles(
   }
 }
 
-// The last block row to finish also closes the refinement step: ||s||^2 (a fixed-order sum of
-// the per-row partials) against tol^2 ||g||^2 sets refine_done, else counts a step.
+// The last block row to arrive also closes the refinement step: ||s||^2 (a fixed-order sum of
+// the per-block-row norms) against tol^2 ||g||^2 sets refine_done, else counts a step.  The
+// norms travel as messages (slots holding kEmpty until written, restored by the closing
+// workgroup), so no workgroup needs a fence, which would write back and invalidate the cache.
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_symv_combine(
     int T, const double* __restrict__ mu_dev, const double* __restrict__ g,
     const double* __restrict__ d, const double* __restrict__ prow,
-    const double* __restrict__ pcol, double* __restrict__ s, double* __restrict__ s_part,
-    LMState* lm, int gate, SyncArea* sync, double tol2) {
+    const double* __restrict__ pcol, double* __restrict__ s, uint64_t* norms, LMState* lm,
+    int gate, SyncArea* sync, double tol2) {
   if (gated(lm, gate)) return;
   __shared__ double sh[kThreads];
   const int B = blockIdx.x;           // block row
@@ -1206,17 +1208,17 @@ __global__ __launch_bounds__(kThreads) void k_symv_combine(
     sq = si * si;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) sq += __shfl_down(sq, off, 64);
-    if (tid == 0) s_part[B] = sq;
+    if (tid == 0) msg_put(norms + B, sq);
   }
   __shared__ int s_last;
-  __threadfence();
-  __syncthreads();
   if (tid == 0) s_last = atomicAdd(&sync->exited, 1u) == gridDim.x - 1;
   __syncthreads();
   if (!s_last) return;
-  __threadfence();
   double v = 0.0;
-  for (int i = tid; i < T; i += kThreads) v += s_part[i];
+  for (int i = tid; i < T; i += kThreads) {
+    v += __longlong_as_double((long long)msg_wait(norms + i, sync, &lm->timeout));
+    __hip_atomic_store(norms + i, kEmpty, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
   sh[tid] = v;
   __syncthreads();
   for (int w = kThreads / 2; w > 0; w >>= 1) {
@@ -1313,7 +1315,7 @@ hipError_t launch_fill_empty(uint64_t* p, int n, hipStream_t st) {
 
 template <typename R>
 hipError_t launch_refine_resid(const R* Hc, int ld, int n_pad, const double* mu_dev,
-                               const double* g, const double* d, double* s, double* s_part,
+                               const double* g, const double* d, double* s, uint64_t* norms,
                                double* prow, double* pcol, LMState* lm, int gate,
                                SyncArea* sync, double tol2, hipStream_t st) {
   const int T = n_pad / 64;
@@ -1321,7 +1323,7 @@ hipError_t launch_refine_resid(const R* Hc, int ld, int n_pad, const double* mu_
   hipLaunchKernelGGL(k_symv_tiles<R>, dim3(ntiles), dim3(kThreads), 0, st, Hc, (int64_t)ld, T, d,
                      prow, pcol, lm, gate);
   hipLaunchKernelGGL(k_symv_combine<R>, dim3(T), dim3(kThreads), 0, st, T, mu_dev, g, d, prow,
-                     pcol, s, s_part, lm, gate, sync, tol2);
+                     pcol, s, norms, lm, gate, sync, tol2);
   return hipGetLastError();
 }
 
@@ -1345,8 +1347,9 @@ hipError_t set_chol_smem_attr() {
                                      double*, uint64_t*, uint64_t*, SyncArea*, int32_t*,       \
                                      const LMState*, int, hipStream_t);                        \
   template hipError_t launch_refine_resid<R>(const R*, int, int, const double*, const double*, \
-                                             const double*, double*, double*, double*, double*, \
-                                             LMState*, int, SyncArea*, double, hipStream_t);
+                                             const double*, double*, uint64_t*, double*,        \
+                                             double*, LMState*, int, SyncArea*, double,         \
+                                             hipStream_t);
 DDC_INST(float)
 DDC_INST(double)
 #undef DDC_INST

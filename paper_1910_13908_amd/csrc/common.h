@@ -136,12 +136,14 @@ hipError_t launch_cost_adjoint(const ObsDev& o, int K, const R* res, const R* co
 
 // k_chol.hip
 // Factor H + mu I (mu from mu_dev if non-null); with g != null also y = L^{-1} g.
-// part: scratch of [T][2][4096] elements for the diagonal partial sums; flags: T(T+1)/2 + T.
+// part: scratch of T * 2 * 4096 * 8 bytes for the diagonal partial sums (FP32: tagged with
+// seq, which must differ from every earlier launch's on the same scratch and be nonzero on
+// zeroed scratch); flags: T(T+1)/2 + T.
 template <typename R>
 hipError_t launch_cholesky(const R* Hc, int ld, int n_pad, const double* mu_dev, double mu_host,
-                           const double* g, double* y, R* Lt, R* Linv, R* part, SyncArea* sync,
-                           uint32_t* flags, uint32_t* yflags, int32_t* status, hipStream_t st,
-                           int n_wg);
+                           const double* g, double* y, R* Lt, R* Linv, void* part,
+                           uint32_t seq, SyncArea* sync, uint32_t* flags, uint32_t* yflags,
+                           int32_t* status, hipStream_t st, int n_wg);
 // dst tile t = transpose of src tile t for ntiles packed 64x64 tiles, and likewise dst2/src2
 // for ntiles2 tiles, in one launch (the backward solve reads the transposed factor and
 // inverses); skipped when lm reports a failed factorisation.

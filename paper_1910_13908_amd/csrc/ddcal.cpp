@@ -56,6 +56,7 @@ struct ddc_ctx {
   std::vector<hipEvent_t> pool;
   TimerAcc acc[T_COUNT];
   int chol_wg = 512;
+  uint32_t chol_seq = 0;         // tag of the factorisation's partial-sum messages
 
   LMState* lm() { return reinterpret_cast<LMState*>(sync); }
   SyncArea* area(int i) { return reinterpret_cast<SyncArea*>(sync + 512 + 64 * i); }
@@ -248,7 +249,7 @@ void layout_solve(Bump& bp, SolveBufs& b, int n, size_t es, int64_t B, int64_t n
   const size_t ntiles = (size_t)b.T * (b.T + 1) / 2;
   offs.push_back(bp.take(ntiles * 64 * sizeof(double)));               // prow
   offs.push_back(bp.take(ntiles * 64 * sizeof(double)));               // pcol
-  offs.push_back(bp.take((size_t)b.T * 2 * 4096 * es));                 // Cholesky partial sums
+  offs.push_back(bp.take((size_t)b.T * 2 * 4096 * 8));                  // Cholesky partial sums
   offs.push_back(bp.take((size_t)b.T * (b.T + 1) / 2 * 4096 * es));    // LtT (transposed tiles)
   offs.push_back(bp.take((size_t)b.T * 4096 * es));                    // LinvT
 }
@@ -271,6 +272,8 @@ void bind_solve(ddc_ctx* c, SolveBufs& b, const std::vector<size_t>& o) {
   b.prow = reinterpret_cast<double*>(w + o[13]);
   b.pcol = reinterpret_cast<double*>(w + o[14]);
   b.cpart = w + o[15];
+  // the factorisation's FP32 partial-sum messages carry nonzero tags: zeroed scratch holds none
+  (void)hipMemsetAsync(b.cpart, 0, (size_t)b.T * 2 * 4096 * 8, c->stream);
   b.LtT = w + o[16];
   b.LinvT = w + o[17];
   b.h_off = o[0];
@@ -303,9 +306,9 @@ ddc_status enqueue_solve(ddc_ctx* c, SolveBufs& b, LMState* lm, int refine_max, 
   R* LiT = reinterpret_cast<R*>(b.LinvT);
   // the factorisation also runs the forward substitution y = L^{-1} g
   DDCCK(timed(c, T_CHOL, chol_flop(b.n), [&] {
-    return launch_cholesky<R>(Hc, b.ld, b.n_pad, &lm->mu_eff, 0.0, b.g, b.y, Lt, Li,
-                              reinterpret_cast<R*>(b.cpart), c->area(0), c->chol_flags(),
-                              c->fwd_flags(), &lm->notpd, st, c->chol_wg);
+    return launch_cholesky<R>(Hc, b.ld, b.n_pad, &lm->mu_eff, 0.0, b.g, b.y, Lt, Li, b.cpart,
+                              ++c->chol_seq, c->area(0), c->chol_flags(), c->fwd_flags(),
+                              &lm->notpd, st, c->chol_wg);
   }));
   // transposed copies of the factor and inverse tiles: the backward solves read them by rows
   HIPCK(launch_transpose_tiles<R>(Lt, LtT, b.T * (b.T + 1) / 2, Li, LiT, b.T, lm, st));

@@ -527,6 +527,61 @@ __device__ __forceinline__ void acc_load_h(typename Mfma<R>::acc_t (&acc)[2][2],
       }
 }
 
+// Look-ahead partial sums in FP32 travel as tagged messages: each 64-bit slot holds a value and
+// the launch's sequence number, so the diagonal worker reads them as soon as they exist, with
+// no flag, no fence and no clearing between launches.  Slot (tile s, which, k, thread) sits at
+// ((s * 2 + which) * 16 + k) * kThreads + thread, so a wave's accesses are contiguous.
+__device__ __forceinline__ uint64_t* tagged_slots(void* base, int s, int which) {
+  return reinterpret_cast<uint64_t*>(base) + (int64_t)(s * 2 + which) * 16 * kThreads;
+}
+__device__ __forceinline__ void tagged_put16(uint64_t* p, uint32_t seq,
+                                             const Mfma<float>::acc_t (&acc)[2][2]) {
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int k = (bi * 2 + bj) * 4 + v;
+        const uint64_t m = ((uint64_t)seq << 32) | (uint64_t)__float_as_uint(acc[bi][bj][v]);
+        __hip_atomic_store(p + k * kThreads + threadIdx.x, m, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      }
+}
+// acc += the 16 values at p once all carry tag seq; false on abort or time-out.
+__device__ bool tagged_add16(const uint64_t* p, uint32_t seq, Mfma<float>::acc_t (&acc)[2][2],
+                             SyncArea* sync, int32_t* status) {
+  uint32_t spins = 0;
+  for (;;) {
+    uint64_t m[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+      m[k] = __hip_atomic_load(p + k * kThreads + threadIdx.x, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    bool all = true;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) all &= (uint32_t)(m[k] >> 32) == seq;
+    if (all) {
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            acc[bi][bj][v] += __uint_as_float((uint32_t)m[(bi * 2 + bj) * 4 + v]);
+      return true;
+    }
+    if (__hip_atomic_load(&sync->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
+      return false;
+    if (++spins > kSpinLimit) {
+      __hip_atomic_store(&sync->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (status) atomicOr(status, 2);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+}
+
 // Roles of the factorisation.  Ticket 0 makes its workgroup the diagonal worker (DW): it
 // factors the diagonal tiles in order, s = 0..T-1, and keeps each inverse in LDS for the next
 // step, so the chain of dependent diagonal factorisations has no inter-workgroup hand-off.
@@ -622,7 +677,7 @@ template <typename R>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_cholesky(
     const R* __restrict__ Hc, int64_t ld, int T, const double* __restrict__ mu_dev, double mu_host,
     const double* __restrict__ gvec, double* __restrict__ yvec, R* __restrict__ Lt,
-    R* __restrict__ Linv, R* __restrict__ part, SyncArea* sync, uint32_t* flags,
+    R* __restrict__ Linv, void* part_raw, uint32_t seq, SyncArea* sync, uint32_t* flags,
     uint32_t* yflags, int32_t* status) {
   constexpr int STR = Mfma<R>::STR;
   constexpr int TILE = 64 * STR;
@@ -638,7 +693,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
   const uint32_t ntasks = chol_tasks(T);
   const uint32_t ntile_flags = (uint32_t)(T * (T + 1) / 2);
   uint32_t* daflags = flags + ntile_flags;
-  // raw per-thread layout of one accumulator tile: thread tid owns 16 values
+  // FP64: raw per-thread layout of one accumulator tile, thread tid owns 16 values (published
+  // with a flag); FP32: tagged messages
+  R* part = reinterpret_cast<R*>(part_raw);
   auto part_ptr = [&](int s, int which) { return part + ((int64_t)s * 2 + which) * 4096 + tid * 16; };
 
   for (;;) {
@@ -662,18 +719,23 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
           acc_t accs[2][2];
           acc_load_h<R>(accs, Hc, ld, st, st - 1, 0.0, qr, qc);
           if (st >= 2) {
-            if (ok) ok = wait_flag(daflags + st, sync, status);
-            const R* ps = part_ptr(st, 0);
-            const R* pd = part_ptr(st, 1);
+            if constexpr (sizeof(R) == 4) {
+              if (ok) ok = tagged_add16(tagged_slots(part_raw, st, 0), seq, accs, sync, status);
+              if (ok) ok = tagged_add16(tagged_slots(part_raw, st, 1), seq, accd, sync, status);
+            } else {
+              if (ok) ok = wait_flag(daflags + st, sync, status);
+              const R* ps = part_ptr(st, 0);
+              const R* pd = part_ptr(st, 1);
 #pragma unroll
-            for (int bi = 0; bi < 2; ++bi)
+              for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-              for (int bj = 0; bj < 2; ++bj)
+                for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                  accs[bi][bj][v] += ps[(bi * 2 + bj) * 4 + v];
-                  accd[bi][bj][v] += pd[(bi * 2 + bj) * 4 + v];
-                }
+                  for (int v = 0; v < 4; ++v) {
+                    accs[bi][bj][v] += ps[(bi * 2 + bj) * 4 + v];
+                    accd[bi][bj][v] += pd[(bi * 2 + bj) * 4 + v];
+                  }
+            }
           }
           acc_to_lds<R>(accs, Abuf, qr, qc);
           __syncthreads();
@@ -710,19 +772,25 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj) accs[bi][bj] = accd[bi][bj] = acc_t{0, 0, 0, 0};
       ok = accumulate<R, true>(accs, accd, Lt, T, s, s - 1, s - 1, lds, sync, flags, status, qr, qc);
-      R* ps = part_ptr(s, 0);
-      R* pd = part_ptr(s, 1);
+      if constexpr (sizeof(R) == 4) {
+        tagged_put16(tagged_slots(part_raw, s, 0), seq, accs);
+        tagged_put16(tagged_slots(part_raw, s, 1), seq, accd);
+        __syncthreads();
+      } else {
+        R* ps = part_ptr(s, 0);
+        R* pd = part_ptr(s, 1);
 #pragma unroll
-      for (int bi = 0; bi < 2; ++bi)
+        for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-        for (int bj = 0; bj < 2; ++bj)
+          for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            ps[(bi * 2 + bj) * 4 + v] = accs[bi][bj][v];
-            pd[(bi * 2 + bj) * 4 + v] = accd[bi][bj][v];
-          }
-      publish(daflags + s);
-      __syncthreads();
+            for (int v = 0; v < 4; ++v) {
+              ps[(bi * 2 + bj) * 4 + v] = accs[bi][bj][v];
+              pd[(bi * 2 + bj) * 4 + v] = accd[bi][bj][v];
+            }
+        publish(daflags + s);
+        __syncthreads();
+      }
     } else if (kind == TASK_R) {
       acc_t acc[2][2], dummy[2][2];
       acc_load_h<R>(acc, Hc, ld, I, J, 0.0, qr, qc);
@@ -1271,17 +1339,17 @@ hipError_t launch_transpose_tiles(const R* src, R* dst, int ntiles, const R* src
 
 template <typename R>
 hipError_t launch_cholesky(const R* Hc, int ld, int n_pad, const double* mu_dev, double mu_host,
-                           const double* g, double* y, R* Lt, R* Linv, R* part, SyncArea* sync,
-                           uint32_t* flags, uint32_t* yflags, int32_t* status, hipStream_t st,
-                           int n_wg) {
+                           const double* g, double* y, R* Lt, R* Linv, void* part,
+                           uint32_t seq, SyncArea* sync, uint32_t* flags, uint32_t* yflags,
+                           int32_t* status, hipStream_t st, int n_wg) {
   const int T = n_pad / 64;
   const int ntasks = (int)chol_tasks(T);
   // at least two workgroups: the diagonal worker and one for the other tasks
   int grid = n_wg < ntasks ? n_wg : ntasks;
   if (grid < 2) grid = 2;
   hipLaunchKernelGGL(k_cholesky<R>, dim3(grid), dim3(kThreads), chol_smem_bytes<R>(), st, Hc,
-                     (int64_t)ld, T, mu_dev, mu_host, g, y, Lt, Linv, part, sync, flags, yflags,
-                     status);
+                     (int64_t)ld, T, mu_dev, mu_host, g, y, Lt, Linv, part, seq, sync, flags,
+                     yflags, status);
   return hipGetLastError();
 }
 
@@ -1339,8 +1407,9 @@ hipError_t set_chol_smem_attr() {
 
 #define DDC_INST(R)                                                                           \
   template hipError_t launch_cholesky<R>(const R*, int, int, const double*, double,             \
-                                         const double*, double*, R*, R*, R*, SyncArea*,        \
-                                         uint32_t*, uint32_t*, int32_t*, hipStream_t, int);    \
+                                         const double*, double*, R*, R*, void*, uint32_t,      \
+                                         SyncArea*, uint32_t*, uint32_t*, int32_t*,            \
+                                         hipStream_t, int);                                    \
   template hipError_t launch_transpose_tiles<R>(const R*, R*, int, const R*, R*, int,           \
                                                 const LMState*, hipStream_t);                  \
   template hipError_t launch_trsv<R>(bool, const R*, const R*, int, const double*, double*,    \

@@ -145,7 +145,8 @@ __device__ __forceinline__ void publish(uint32_t* flag) {
 
 // Leave the persistent loop; the last workgroup out clears the flags and the counters.
 __device__ void exit_and_reset(SyncArea* sync, uint32_t* flags, int nflags,
-                               uint32_t* flags2 = nullptr, int nflags2 = 0) {
+                               uint32_t* flags2 = nullptr, int nflags2 = 0,
+                               uint64_t* msgs = nullptr, int nmsgs = 0) {
   __shared__ int s_last;
   __threadfence();
   __syncthreads();
@@ -155,6 +156,8 @@ __device__ void exit_and_reset(SyncArea* sync, uint32_t* flags, int nflags,
     __threadfence();
     for (int i = threadIdx.x; i < nflags; i += blockDim.x) flags[i] = 0u;
     for (int i = threadIdx.x; i < nflags2; i += blockDim.x) flags2[i] = 0u;
+    for (int i = threadIdx.x; i < nmsgs; i += blockDim.x)   // the "empty" message pattern
+      __hip_atomic_store(msgs + i, 0x7FF4DD0000000001ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (threadIdx.x == 0) {
       sync->ticket = 0u;
       sync->exited = 0u;
@@ -527,6 +530,63 @@ __device__ __forceinline__ void acc_load_h(typename Mfma<R>::acc_t (&acc)[2][2],
       }
 }
 
+// Messages: 64-bit slots written and read with agent-scope relaxed atomics; a slot holding
+// kEmpty (a signalling-NaN payload that no arithmetic result carries) is not written yet.
+constexpr uint64_t kEmpty = 0x7FF4DD0000000001ull;
+
+__device__ __forceinline__ uint64_t msg_get(uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void msg_put(uint64_t* p, double v) {
+  __hip_atomic_store(p, (uint64_t)__double_as_longlong(v), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Per-lane bounded poll of one message slot; on abort or time-out returns kEmpty (the caller
+// carries on with garbage; the status word reports the failure).
+__device__ uint64_t msg_wait(uint64_t* p, SyncArea* sync, int32_t* status) {
+  uint32_t spins = 0;
+  uint64_t m;
+  while ((m = msg_get(p)) == kEmpty) {
+    if (__hip_atomic_load(&sync->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
+    if (++spins > kSpinLimit) {
+      __hip_atomic_store(&sync->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (status) atomicOr(status, 2);
+      break;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+  return m;
+}
+
+// v[j] = the doubles at p + off(j) once none holds kEmpty (bounded poll).
+template <typename F>
+__device__ bool msg_get16(const uint64_t* p, F off, double (&v)[16], SyncArea* sync,
+                          int32_t* status) {
+  uint32_t spins = 0;
+  for (;;) {
+    uint64_t m[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+      m[j] = __hip_atomic_load(p + off(j), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    bool all = true;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      all &= m[j] != kEmpty;
+      v[j] = __longlong_as_double((long long)m[j]);
+    }
+    if (all) return true;
+    if (__hip_atomic_load(&sync->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
+      return false;
+    if (++spins > kSpinLimit) {
+      __hip_atomic_store(&sync->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (status) atomicOr(status, 2);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+}
+
 // Look-ahead partial sums in FP32 travel as tagged messages: each 64-bit slot holds a value and
 // the launch's sequence number, so the diagonal worker reads them as soon as they exist, with
 // no flag, no fence and no clearing between launches.  Slot (tile s, which, k, thread) sits at
@@ -582,6 +642,62 @@ __device__ bool tagged_add16(const uint64_t* p, uint32_t seq, Mfma<float>::acc_t
   }
 }
 
+// The diagonal worker's own outputs, the subdiagonal tile L_{s,s-1} and the inverse X_s, are
+// also written (FP32) as tagged copies in natural row-major order, slot e = element e, and read
+// from there by the tasks that need them, so the worker publishes no flag and runs no fence.
+// Copy `which` (0: L_{s,s-1}, 1: X_s) of step s sits after the partial-sum messages.
+__device__ __forceinline__ uint64_t* dw_slots(void* base, int T, int which, int s) {
+  return reinterpret_cast<uint64_t*>(base) + (int64_t)T * 2 * 16 * kThreads +
+         ((int64_t)which * T + s) * 4096;
+}
+// FP32: the forward-substitution blocks y_K as messages (T x 64 slots, kEmpty between launches)
+__device__ __forceinline__ uint64_t* y_slots(void* base, int T) {
+  return reinterpret_cast<uint64_t*>(base) + (int64_t)T * 2 * 16 * kThreads + (int64_t)2 * T * 4096;
+}
+__device__ __forceinline__ void tagged_put(uint64_t* p, uint32_t seq, float v) {
+  __hip_atomic_store(p, ((uint64_t)seq << 32) | (uint64_t)__float_as_uint(v), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+// v[j] = element base_e[j] of a tagged tile once all 16 carry tag seq (bounded poll).
+template <typename F>
+__device__ bool tagged_get16(const uint64_t* t, uint32_t seq, F elem, float (&v)[16],
+                             SyncArea* sync, int32_t* status) {
+  uint32_t spins = 0;
+  for (;;) {
+    uint64_t m[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+      m[j] = __hip_atomic_load(t + elem(j), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    bool all = true;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      all &= (uint32_t)(m[j] >> 32) == seq;
+      v[j] = __uint_as_float((uint32_t)m[j]);
+    }
+    if (all) return true;
+    if (__hip_atomic_load(&sync->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
+      return false;
+    if (++spins > kSpinLimit) {
+      __hip_atomic_store(&sync->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (status) atomicOr(status, 2);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+}
+// The tile_fetch layout (thread t holds elements 4 (t + 256 i) .. + 3, i = 0..3) from a tagged tile.
+__device__ __forceinline__ bool tagged_tile_fetch(const uint64_t* t, uint32_t seq,
+                                                  TileRegs<float>& r, SyncArea* sync,
+                                                  int32_t* status) {
+  float v[16];
+  const int tid = threadIdx.x;
+  const bool ok = tagged_get16(t, seq, [&](int j) { return 4 * (tid + kThreads * (j >> 2)) + (j & 3); },
+                               v, sync, status);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) r.v[i] = f32x4{v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]};
+  return ok;
+}
+
 // Roles of the factorisation.  Ticket 0 makes its workgroup the diagonal worker (DW): it
 // factors the diagonal tiles in order, s = 0..T-1, and keeps each inverse in LDS for the next
 // step, so the chain of dependent diagonal factorisations has no inter-workgroup hand-off.
@@ -627,24 +743,43 @@ __host__ __device__ inline uint32_t chol_tasks(int T) {
 // Accumulate acc1 -= A_K B_K^T (and acc2 -= A_K A_K^T when TWO) over K < nK, where
 // A_K = L(IA, K), B_K = L(IB, K), with a double-buffered LDS pipeline: the next pair of
 // tiles is fetched into registers while the current pair feeds the MFMAs.
+// In both callers IB = nK, so the last B operand L(IB, IB-1) is the diagonal worker's
+// subdiagonal tile: in FP32 it comes from the tagged copy (no flag), every other operand from
+// the factor after its flag.
 template <typename R, bool TWO>
 __device__ __forceinline__ bool accumulate(typename Mfma<R>::acc_t (&acc1)[2][2],
                                            typename Mfma<R>::acc_t (&acc2)[2][2],
                            const R* __restrict__ Lt, int T, int IA, int IB, int nK, R* lds,
-                           SyncArea* sync, uint32_t* flags, int32_t* status, int qr, int qc) {
+                           SyncArea* sync, uint32_t* flags, int32_t* status, int qr, int qc,
+                           void* tagbase, uint32_t seq) {
   constexpr int STR = Mfma<R>::STR;
   constexpr int TILE = 64 * STR;
+  constexpr bool TAG = sizeof(R) == 4;
   if (nK <= 0) return true;
   TileRegs<R> ra, rb;
   // flags of the first `ready` K are known set (and acquired); wait on the rest one by one
-  const int ready = ready_prefix(flags, T, IA, IB, nK);
+  const int ready = ready_prefix(flags, T, IA, IB, TAG ? nK - 1 : nK);
   bool ok = true;
-  if (ready < 1) {
-    ok = wait_flag(flags + tile_index(IA, 0, T), sync, status);
-    if (ok && IB != IA) ok = wait_flag(flags + tile_index(IB, 0, T), sync, status);
-  }
-  tile_fetch<R>(Lt + (int64_t)tile_index(IA, 0, T) * 4096, ra);
-  tile_fetch<R>(Lt + (int64_t)tile_index(IB, 0, T) * 4096, rb);
+  auto wait_k = [&](int K) {
+    if (K < ready || !ok) return;
+    ok = wait_flag(flags + tile_index(IA, K, T), sync, status);
+    const bool b_tagged = TAG && K == nK - 1;
+    if (ok && IB != IA && !b_tagged) ok = wait_flag(flags + tile_index(IB, K, T), sync, status);
+  };
+  auto fetch_k = [&](int K) {
+    tile_fetch<R>(Lt + (int64_t)tile_index(IA, K, T) * 4096, ra);
+    if constexpr (TAG) {
+      if (K == nK - 1) {
+        // per-thread poll; the result is made uniform, as ok decides on barriers
+        const bool g = tagged_tile_fetch(dw_slots(tagbase, T, 0, IB), seq, rb, sync, status);
+        ok = __syncthreads_and(ok && g) != 0;
+        return;
+      }
+    }
+    tile_fetch<R>(Lt + (int64_t)tile_index(IB, K, T) * 4096, rb);
+  };
+  wait_k(0);
+  fetch_k(0);
   tile_stash<R>(ra, lds);
   tile_stash<R>(rb, lds + TILE);
   __syncthreads();
@@ -652,12 +787,8 @@ __device__ __forceinline__ bool accumulate(typename Mfma<R>::acc_t (&acc1)[2][2]
   for (int K = 0; K < nK; ++K) {
     const bool more = K + 1 < nK;
     if (more && ok) {
-      if (K + 1 >= ready) {
-        ok = wait_flag(flags + tile_index(IA, K + 1, T), sync, status);
-        if (ok && IB != IA) ok = wait_flag(flags + tile_index(IB, K + 1, T), sync, status);
-      }
-      tile_fetch<R>(Lt + (int64_t)tile_index(IA, K + 1, T) * 4096, ra);
-      tile_fetch<R>(Lt + (int64_t)tile_index(IB, K + 1, T) * 4096, rb);
+      wait_k(K + 1);
+      fetch_k(K + 1);
     }
     const R* As = lds + buf * 2 * TILE;
     tile_mma<R, true>(acc1, As, As + TILE, qr, qc);
@@ -747,7 +878,22 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
           tile_mma<R, false>(ls, Abuf, Xprev, qr, qc);      // L_{s,s-1} = A X_{s-1}^T
           acc_to_global<R>(ls, Lt + (int64_t)tile_index(st, st - 1, T) * 4096, qr, qc);
           acc_to_lds<R>(ls, Lbuf, qr, qc);
-          publish(flags + tile_index(st, st - 1, T));
+          if constexpr (sizeof(R) == 4) {
+            uint64_t* tl = dw_slots(part_raw, T, 0, st);
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+              for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                  const int r = qr * 32 + bi * 16 + out_row<R>(tid & 63, v);
+                  const int c = qc * 32 + bj * 16 + out_col(tid & 63, v);
+                  tagged_put(tl + r * 64 + c, seq, ls[bi][bj][v]);
+                }
+            __syncthreads();
+          } else {
+            publish(flags + tile_index(st, st - 1, T));
+          }
           __syncthreads();
           tile_mma<R, true>(accd, Lbuf, Lbuf, qr, qc);
           __syncthreads();
@@ -757,8 +903,18 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
         const int bad = cholinv_tile<R>(Abuf, Xcur, rdiag);
         if (bad && tid == 0 && status) atomicOr(status, 1);
         R* dstX = Linv + (int64_t)st * 4096;
-        for (int e = tid; e < 4096; e += kThreads) dstX[e] = Xcur[(e >> 6) * STR + (e & 63)];
-        publish(flags + tile_index(st, st, T));
+        if constexpr (sizeof(R) == 4) {
+          uint64_t* tx = dw_slots(part_raw, T, 1, st);
+          for (int e = tid; e < 4096; e += kThreads) {
+            const R xv = Xcur[(e >> 6) * STR + (e & 63)];
+            dstX[e] = xv;
+            tagged_put(tx + e, seq, xv);
+          }
+          __syncthreads();
+        } else {
+          for (int e = tid; e < 4096; e += kThreads) dstX[e] = Xcur[(e >> 6) * STR + (e & 63)];
+          publish(flags + tile_index(st, st, T));
+        }
         __syncthreads();
         R* tmp = Xprev;
         Xprev = Xcur;
@@ -771,7 +927,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
       for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj) accs[bi][bj] = accd[bi][bj] = acc_t{0, 0, 0, 0};
-      ok = accumulate<R, true>(accs, accd, Lt, T, s, s - 1, s - 1, lds, sync, flags, status, qr, qc);
+      ok = accumulate<R, true>(accs, accd, Lt, T, s, s - 1, s - 1, lds, sync, flags, status, qr, qc,
+                               part_raw, seq);
       if constexpr (sizeof(R) == 4) {
         tagged_put16(tagged_slots(part_raw, s, 0), seq, accs);
         tagged_put16(tagged_slots(part_raw, s, 1), seq, accd);
@@ -794,10 +951,18 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
     } else if (kind == TASK_R) {
       acc_t acc[2][2], dummy[2][2];
       acc_load_h<R>(acc, Hc, ld, I, J, 0.0, qr, qc);
-      ok = accumulate<R, false>(acc, dummy, Lt, T, I, J, J, lds, sync, flags, status, qr, qc);
-      if (ok) ok = wait_flag(flags + tile_index(J, J, T), sync, status);
+      ok = accumulate<R, false>(acc, dummy, Lt, T, I, J, J, lds, sync, flags, status, qr, qc,
+                                part_raw, seq);
       acc_to_lds<R>(acc, lds, qr, qc);
-      tile_to_lds<R>(Linv + (int64_t)J * 4096, lds + TILE);
+      if constexpr (sizeof(R) == 4) {
+        TileRegs<R> xr;
+        const bool g = tagged_tile_fetch(dw_slots(part_raw, T, 1, J), seq, xr, sync, status);
+        ok = __syncthreads_and(ok && g) != 0;
+        tile_stash<R>(xr, lds + TILE);
+      } else {
+        if (ok) ok = wait_flag(flags + tile_index(J, J, T), sync, status);
+        tile_to_lds<R>(Linv + (int64_t)J * 4096, lds + TILE);
+      }
       __syncthreads();
       acc_t out[2][2];
 #pragma unroll
@@ -809,35 +974,77 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
       publish(flags + tile_index(I, J, T));
       __syncthreads();
     } else if (kind == TASK_Y && gvec) {
-      // y_J = X_JJ (g_J - sum_{K<J} L_JK y_K), FP64 accumulation
+      // y_J = X_JJ (g_J - sum_{K<J} L_JK y_K), FP64 accumulation.  FP32: the blocks y_K come
+      // as messages and L_{J,J-1}, X_J from the worker's tagged copies, so only the flags of
+      // the other factor tiles are waited on (one acquire for the prefix already set)
       const int r = tid & 63, pt = tid >> 6;
       double acc = 0.0;
-      for (int K = 0; K < J && ok; ++K) {
-        ok = wait_flag(flags + tile_index(J, K, T), sync, status);
-        if (ok) ok = wait_flag(yflags + K, sync, status);
-        const R* tile = Lt + (int64_t)tile_index(J, K, T) * 4096 + r * 64 + pt * 16;
-        const double* yv = yvec + 64 * K + pt * 16;
+      float iv[16];
+      if constexpr (sizeof(R) == 4) {
+        uint64_t* ymsg = y_slots(part_raw, T);
+        const int nf = J >= 1 ? J - 1 : 0;          // K < J-1: tiles of the R tasks
+        const int ready = ready_prefix(flags, T, J, J, nf);
+        for (int K = 0; K < J && ok; ++K) {
+          float lv[16];
+          if (K < nf) {
+            if (K >= ready) ok = wait_flag(flags + tile_index(J, K, T), sync, status);
+            const R* tile = Lt + (int64_t)tile_index(J, K, T) * 4096 + r * 64 + pt * 16;
 #pragma unroll
-        for (int c = 0; c < 16; ++c) acc = fma((double)tile[c], yv[c], acc);
+            for (int c = 0; c < 16; ++c) lv[c] = tile[c];
+          }
+          bool g = true;
+          if (K >= nf)
+            g = tagged_get16(dw_slots(part_raw, T, 0, J), seq,
+                             [&](int c) { return r * 64 + pt * 16 + c; }, lv, sync, status);
+          double yk[16];
+          g = msg_get16(ymsg + 64 * K + pt * 16, [](int c) { return c; }, yk, sync, status) && g;
+          // per-thread polls; ok decides the loop and the flag waits, so it is made uniform
+          ok = __syncthreads_and(ok && g) != 0;
+#pragma unroll
+          for (int c = 0; c < 16; ++c) acc = fma((double)lv[c], yk[c], acc);
+        }
+        const bool g = tagged_get16(dw_slots(part_raw, T, 1, J), seq,
+                                    [&](int c) { return r * 64 + pt * 16 + c; }, iv, sync, status);
+        ok = __syncthreads_and(ok && g) != 0;
+      } else {
+        for (int K = 0; K < J && ok; ++K) {
+          ok = wait_flag(flags + tile_index(J, K, T), sync, status);
+          if (ok) ok = wait_flag(yflags + K, sync, status);
+          const R* tile = Lt + (int64_t)tile_index(J, K, T) * 4096 + r * 64 + pt * 16;
+          const double* yv = yvec + 64 * K + pt * 16;
+#pragma unroll
+          for (int c = 0; c < 16; ++c) acc = fma((double)tile[c], yv[c], acc);
+        }
       }
       s_red[tid] = acc;
       __syncthreads();
       if (tid < 64)
         s_vec[tid] = gvec[64 * J + tid] - (((s_red[tid] + s_red[tid + 64]) + s_red[tid + 128]) + s_red[tid + 192]);
-      if (ok) ok = wait_flag(flags + tile_index(J, J, T), sync, status);
-      const R* inv = Linv + (int64_t)J * 4096 + r * 64 + pt * 16;
       double y = 0.0;
+      if constexpr (sizeof(R) == 4) {
+        __syncthreads();
 #pragma unroll
-      for (int c = 0; c < 16; ++c) y = fma((double)inv[c], s_vec[pt * 16 + c], y);
+        for (int c = 0; c < 16; ++c) y = fma((double)iv[c], s_vec[pt * 16 + c], y);
+      } else {
+        if (ok) ok = wait_flag(flags + tile_index(J, J, T), sync, status);
+        const R* inv = Linv + (int64_t)J * 4096 + r * 64 + pt * 16;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) y = fma((double)inv[c], s_vec[pt * 16 + c], y);
+      }
       s_red[tid] = y;
       __syncthreads();
-      if (tid < 64)
-        yvec[64 * J + tid] = ((s_red[tid] + s_red[tid + 64]) + s_red[tid + 128]) + s_red[tid + 192];
-      publish(yflags + J);
+      if (tid < 64) {
+        const double yj = ((s_red[tid] + s_red[tid + 64]) + s_red[tid + 128]) + s_red[tid + 192];
+        yvec[64 * J + tid] = yj;
+        if constexpr (sizeof(R) == 4) msg_put(y_slots(part_raw, T) + 64 * J + tid, yj);
+      }
+      if constexpr (sizeof(R) != 4) publish(yflags + J);
       __syncthreads();
     }
   }
-  exit_and_reset(sync, flags, (int)(ntile_flags + (uint32_t)T), yflags, yflags ? T : 0);
+  // FP32: the last workgroup out also restores kEmpty in the y messages
+  exit_and_reset(sync, flags, (int)(ntile_flags + (uint32_t)T), yflags, yflags ? T : 0,
+                 sizeof(R) == 4 ? y_slots(part_raw, T) : nullptr, sizeof(R) == 4 ? 64 * T : 0);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -906,33 +1113,6 @@ __device__ __forceinline__ double quad_sum(double v) {
   v += dpp_quad<0xB1>(v);      // quad_perm [1,0,3,2]: partner lane ^ 1
   return v + dpp_quad<0x4E>(v);  // quad_perm [2,3,0,1]: partner lane ^ 2
 }
-constexpr uint64_t kEmpty = 0x7FF4DD0000000001ull;
-
-__device__ __forceinline__ uint64_t msg_get(uint64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void msg_put(uint64_t* p, double v) {
-  __hip_atomic_store(p, (uint64_t)__double_as_longlong(v), __ATOMIC_RELAXED,
-                     __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Per-lane bounded poll of one message slot; on abort or time-out returns kEmpty (the caller
-// carries on with garbage; the status word reports the failure).
-__device__ uint64_t msg_wait(uint64_t* p, SyncArea* sync, int32_t* status) {
-  uint32_t spins = 0;
-  uint64_t m;
-  while ((m = msg_get(p)) == kEmpty) {
-    if (__hip_atomic_load(&sync->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
-    if (++spins > kSpinLimit) {
-      __hip_atomic_store(&sync->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (status) atomicOr(status, 2);
-      break;
-    }
-    __builtin_amdgcn_s_sleep(2);
-  }
-  return m;
-}
-
 template <bool FWD>
 __device__ __forceinline__ int solve_block(int T, int q) { return FWD ? q : T - 1 - q; }
 

@@ -249,8 +249,9 @@ void layout_solve(Bump& bp, SolveBufs& b, int n, size_t es, int64_t B, int64_t n
   const size_t ntiles = (size_t)b.T * (b.T + 1) / 2;
   offs.push_back(bp.take(ntiles * 64 * sizeof(double)));               // prow
   offs.push_back(bp.take(ntiles * 64 * sizeof(double)));               // pcol
-  // Cholesky messages: partial sums (T x 2 tiles), the worker's tagged tiles (2 T), y blocks
-  offs.push_back(bp.take(((size_t)b.T * 2 * 4096 + (size_t)2 * b.T * 4096 + (size_t)64 * b.T) * 8));
+  // Cholesky messages: partial sums (T x 2 tiles), tagged copies of the lower tiles, y blocks
+  offs.push_back(bp.take(((size_t)b.T * 2 * 4096 + (size_t)b.T * (b.T + 1) / 2 * 4096 +
+                          (size_t)64 * b.T) * 8));
   offs.push_back(bp.take((size_t)b.T * (b.T + 1) / 2 * 4096 * es));    // LtT (transposed tiles)
   offs.push_back(bp.take((size_t)b.T * 4096 * es));                    // LinvT
 }
@@ -275,7 +276,7 @@ void bind_solve(ddc_ctx* c, SolveBufs& b, const std::vector<size_t>& o) {
   b.cpart = w + o[15];
   // the factorisation's FP32 tagged messages carry nonzero tags (zeroed scratch holds none);
   // its y messages start empty
-  const size_t ntag = (size_t)b.T * 2 * 4096 + (size_t)2 * b.T * 4096;
+  const size_t ntag = (size_t)b.T * 2 * 4096 + (size_t)b.T * (b.T + 1) / 2 * 4096;
   (void)hipMemsetAsync(b.cpart, 0, ntag * 8, c->stream);
   (void)launch_fill_empty(reinterpret_cast<uint64_t*>(b.cpart) + ntag, 64 * b.T, c->stream);
   b.LtT = w + o[16];

@@ -642,21 +642,40 @@ __device__ bool tagged_add16(const uint64_t* p, uint32_t seq, Mfma<float>::acc_t
   }
 }
 
-// The diagonal worker's own outputs, the subdiagonal tile L_{s,s-1} and the inverse X_s, are
-// also written (FP32) as tagged copies in natural row-major order, slot e = element e, and read
-// from there by the tasks that need them, so the worker publishes no flag and runs no fence.
-// Copy `which` (0: L_{s,s-1}, 1: X_s) of step s sits after the partial-sum messages.
-__device__ __forceinline__ uint64_t* dw_slots(void* base, int T, int which, int s) {
-  return reinterpret_cast<uint64_t*>(base) + (int64_t)T * 2 * 16 * kThreads +
-         ((int64_t)which * T + s) * 4096;
+// In FP32 every tile a task hands to another (L_IJ, and in the slot of the diagonal tile
+// (s, s) the inverse X_s) is also written as a tagged copy in natural row-major order, slot e =
+// element e, and read from there, so no task publishes a flag or runs a fence.  The copies sit
+// after the partial-sum messages, tile t at t * 4096 (column-major tile order).
+__device__ __forceinline__ uint64_t* tile_slots(void* base, int T, uint32_t ti) {
+  return reinterpret_cast<uint64_t*>(base) + (int64_t)T * 2 * 16 * kThreads + (int64_t)ti * 4096;
 }
 // FP32: the forward-substitution blocks y_K as messages (T x 64 slots, kEmpty between launches)
 __device__ __forceinline__ uint64_t* y_slots(void* base, int T) {
-  return reinterpret_cast<uint64_t*>(base) + (int64_t)T * 2 * 16 * kThreads + (int64_t)2 * T * 4096;
+  return reinterpret_cast<uint64_t*>(base) + (int64_t)T * 2 * 16 * kThreads +
+         (int64_t)T * (T + 1) / 2 * 4096;
 }
+// The 16 elements of thread tid in the MFMA accumulator layout (acc_to_global) as tagged slots.
+__device__ __forceinline__ void tagged_put_acc(uint64_t* t, uint32_t seq,
+                                               const Mfma<float>::acc_t (&acc)[2][2], int qr,
+                                               int qc);
 __device__ __forceinline__ void tagged_put(uint64_t* p, uint32_t seq, float v) {
   __hip_atomic_store(p, ((uint64_t)seq << 32) | (uint64_t)__float_as_uint(v), __ATOMIC_RELAXED,
                      __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void tagged_put_acc(uint64_t* t, uint32_t seq,
+                                               const Mfma<float>::acc_t (&acc)[2][2], int qr,
+                                               int qc) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = qr * 32 + bi * 16 + out_row<float>(lane, v);
+        const int c = qc * 32 + bj * 16 + out_col(lane, v);
+        tagged_put(t + r * 64 + c, seq, acc[bi][bj][v]);
+      }
 }
 // v[j] = element base_e[j] of a tagged tile once all 16 carry tag seq (bounded poll).
 template <typename F>
@@ -743,9 +762,8 @@ __host__ __device__ inline uint32_t chol_tasks(int T) {
 // Accumulate acc1 -= A_K B_K^T (and acc2 -= A_K A_K^T when TWO) over K < nK, where
 // A_K = L(IA, K), B_K = L(IB, K), with a double-buffered LDS pipeline: the next pair of
 // tiles is fetched into registers while the current pair feeds the MFMAs.
-// In both callers IB = nK, so the last B operand L(IB, IB-1) is the diagonal worker's
-// subdiagonal tile: in FP32 it comes from the tagged copy (no flag), every other operand from
-// the factor after its flag.
+// FP32 reads every operand from the tagged copies (no flags); FP64 waits on the tiles' flags
+// (one acquire for the prefix already set, then one by one).
 template <typename R, bool TWO>
 __device__ __forceinline__ bool accumulate(typename Mfma<R>::acc_t (&acc1)[2][2],
                                            typename Mfma<R>::acc_t (&acc2)[2][2],
@@ -757,26 +775,25 @@ __device__ __forceinline__ bool accumulate(typename Mfma<R>::acc_t (&acc1)[2][2]
   constexpr bool TAG = sizeof(R) == 4;
   if (nK <= 0) return true;
   TileRegs<R> ra, rb;
-  // flags of the first `ready` K are known set (and acquired); wait on the rest one by one
-  const int ready = ready_prefix(flags, T, IA, IB, TAG ? nK - 1 : nK);
+  const int ready = TAG ? nK : ready_prefix(flags, T, IA, IB, nK);
   bool ok = true;
   auto wait_k = [&](int K) {
-    if (K < ready || !ok) return;
+    if (TAG || K < ready || !ok) return;
     ok = wait_flag(flags + tile_index(IA, K, T), sync, status);
-    const bool b_tagged = TAG && K == nK - 1;
-    if (ok && IB != IA && !b_tagged) ok = wait_flag(flags + tile_index(IB, K, T), sync, status);
+    if (ok && IB != IA) ok = wait_flag(flags + tile_index(IB, K, T), sync, status);
   };
   auto fetch_k = [&](int K) {
-    tile_fetch<R>(Lt + (int64_t)tile_index(IA, K, T) * 4096, ra);
     if constexpr (TAG) {
-      if (K == nK - 1) {
-        // per-thread poll; the result is made uniform, as ok decides on barriers
-        const bool g = tagged_tile_fetch(dw_slots(tagbase, T, 0, IB), seq, rb, sync, status);
-        ok = __syncthreads_and(ok && g) != 0;
-        return;
-      }
+      // per-thread polls; ok is made uniform once, at the end
+      const bool ga = tagged_tile_fetch(tile_slots(tagbase, T, tile_index(IA, K, T)), seq, ra,
+                                        sync, status);
+      const bool gb = tagged_tile_fetch(tile_slots(tagbase, T, tile_index(IB, K, T)), seq, rb,
+                                        sync, status);
+      ok = ok && ga && gb;
+    } else {
+      tile_fetch<R>(Lt + (int64_t)tile_index(IA, K, T) * 4096, ra);
+      tile_fetch<R>(Lt + (int64_t)tile_index(IB, K, T) * 4096, rb);
     }
-    tile_fetch<R>(Lt + (int64_t)tile_index(IB, K, T) * 4096, rb);
   };
   wait_k(0);
   fetch_k(0);
@@ -786,7 +803,7 @@ __device__ __forceinline__ bool accumulate(typename Mfma<R>::acc_t (&acc1)[2][2]
   int buf = 0;
   for (int K = 0; K < nK; ++K) {
     const bool more = K + 1 < nK;
-    if (more && ok) {
+    if (more && (TAG || ok)) {
       wait_k(K + 1);
       fetch_k(K + 1);
     }
@@ -801,6 +818,7 @@ __device__ __forceinline__ bool accumulate(typename Mfma<R>::acc_t (&acc1)[2][2]
     __syncthreads();
     buf ^= 1;
   }
+  if constexpr (TAG) ok = __syncthreads_and(ok) != 0;
   return ok;
 }
 
@@ -879,17 +897,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
           acc_to_global<R>(ls, Lt + (int64_t)tile_index(st, st - 1, T) * 4096, qr, qc);
           acc_to_lds<R>(ls, Lbuf, qr, qc);
           if constexpr (sizeof(R) == 4) {
-            uint64_t* tl = dw_slots(part_raw, T, 0, st);
-#pragma unroll
-            for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-              for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                  const int r = qr * 32 + bi * 16 + out_row<R>(tid & 63, v);
-                  const int c = qc * 32 + bj * 16 + out_col(tid & 63, v);
-                  tagged_put(tl + r * 64 + c, seq, ls[bi][bj][v]);
-                }
+            tagged_put_acc(tile_slots(part_raw, T, tile_index(st, st - 1, T)), seq, ls, qr, qc);
             __syncthreads();
           } else {
             publish(flags + tile_index(st, st - 1, T));
@@ -904,7 +912,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
         if (bad && tid == 0 && status) atomicOr(status, 1);
         R* dstX = Linv + (int64_t)st * 4096;
         if constexpr (sizeof(R) == 4) {
-          uint64_t* tx = dw_slots(part_raw, T, 1, st);
+          uint64_t* tx = tile_slots(part_raw, T, tile_index(st, st, T));
           for (int e = tid; e < 4096; e += kThreads) {
             const R xv = Xcur[(e >> 6) * STR + (e & 63)];
             dstX[e] = xv;
@@ -956,7 +964,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
       acc_to_lds<R>(acc, lds, qr, qc);
       if constexpr (sizeof(R) == 4) {
         TileRegs<R> xr;
-        const bool g = tagged_tile_fetch(dw_slots(part_raw, T, 1, J), seq, xr, sync, status);
+        const bool g = tagged_tile_fetch(tile_slots(part_raw, T, tile_index(J, J, T)), seq, xr,
+                                         sync, status);
         ok = __syncthreads_and(ok && g) != 0;
         tile_stash<R>(xr, lds + TILE);
       } else {
@@ -971,7 +980,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
         for (int bj = 0; bj < 2; ++bj) out[bi][bj] = acc_t{0, 0, 0, 0};
       tile_mma<R, false>(out, lds, lds + TILE, qr, qc);
       acc_to_global<R>(out, Lt + (int64_t)tile_index(I, J, T) * 4096, qr, qc);
-      publish(flags + tile_index(I, J, T));
+      if constexpr (sizeof(R) == 4) {
+        tagged_put_acc(tile_slots(part_raw, T, tile_index(I, J, T)), seq, out, qr, qc);
+        __syncthreads();
+      } else {
+        publish(flags + tile_index(I, J, T));
+      }
       __syncthreads();
     } else if (kind == TASK_Y && gvec) {
       // y_J = X_JJ (g_J - sum_{K<J} L_JK y_K), FP64 accumulation.  FP32: the blocks y_K come
@@ -982,30 +996,19 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
       float iv[16];
       if constexpr (sizeof(R) == 4) {
         uint64_t* ymsg = y_slots(part_raw, T);
-        const int nf = J >= 1 ? J - 1 : 0;          // K < J-1: tiles of the R tasks
-        const int ready = ready_prefix(flags, T, J, J, nf);
-        for (int K = 0; K < J && ok; ++K) {
+        bool g = true;
+        for (int K = 0; K < J; ++K) {
           float lv[16];
-          if (K < nf) {
-            if (K >= ready) ok = wait_flag(flags + tile_index(J, K, T), sync, status);
-            const R* tile = Lt + (int64_t)tile_index(J, K, T) * 4096 + r * 64 + pt * 16;
-#pragma unroll
-            for (int c = 0; c < 16; ++c) lv[c] = tile[c];
-          }
-          bool g = true;
-          if (K >= nf)
-            g = tagged_get16(dw_slots(part_raw, T, 0, J), seq,
-                             [&](int c) { return r * 64 + pt * 16 + c; }, lv, sync, status);
           double yk[16];
+          g = tagged_get16(tile_slots(part_raw, T, tile_index(J, K, T)), seq,
+                           [&](int c) { return r * 64 + pt * 16 + c; }, lv, sync, status) && g;
           g = msg_get16(ymsg + 64 * K + pt * 16, [](int c) { return c; }, yk, sync, status) && g;
-          // per-thread polls; ok decides the loop and the flag waits, so it is made uniform
-          ok = __syncthreads_and(ok && g) != 0;
 #pragma unroll
           for (int c = 0; c < 16; ++c) acc = fma((double)lv[c], yk[c], acc);
         }
-        const bool g = tagged_get16(dw_slots(part_raw, T, 1, J), seq,
-                                    [&](int c) { return r * 64 + pt * 16 + c; }, iv, sync, status);
-        ok = __syncthreads_and(ok && g) != 0;
+        g = tagged_get16(tile_slots(part_raw, T, tile_index(J, J, T)), seq,
+                         [&](int c) { return r * 64 + pt * 16 + c; }, iv, sync, status) && g;
+        ok = __syncthreads_and(g) != 0;
       } else {
         for (int K = 0; K < J && ok; ++K) {
           ok = wait_flag(flags + tile_index(J, K, T), sync, status);

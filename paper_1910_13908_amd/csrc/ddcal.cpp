@@ -61,7 +61,7 @@ struct ddc_ctx {
   LMState* lm() { return reinterpret_cast<LMState*>(sync); }
   SyncArea* area(int i) { return reinterpret_cast<SyncArea*>(sync + 512 + 64 * i); }
   uint32_t* chol_flags() { return reinterpret_cast<uint32_t*>(sync + 1024); }
-  uint32_t* fwd_flags() { return chol_flags() + kMaxTiles * (kMaxTiles + 1) / 2 + kMaxTiles; }
+  uint32_t* fwd_flags() { return chol_flags() + kMaxTiles * (kMaxTiles + 1) / 2 + 2 * kMaxTiles; }
   uint32_t* bwd_flags() { return fwd_flags() + 2 * kMaxTiles; }
   // triangular-solve message arrays (partial sums, solution blocks), kEmpty between solves
   uint64_t* solve_psum() { return reinterpret_cast<uint64_t*>(sync + (1u << 20)); }

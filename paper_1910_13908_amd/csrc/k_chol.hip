@@ -730,7 +730,7 @@ __device__ __forceinline__ bool tagged_tile_fetch(const uint64_t* t, uint32_t se
 // A task waits only on tasks of earlier groups or on DW steps whose own inputs come from
 // earlier groups, so the schedule cannot deadlock with any number (>= 2) of resident
 // workgroups.
-enum { TASK_DW = 0, TASK_DA = 1, TASK_Y = 2, TASK_R = 3, TASK_NONE = 4 };
+enum { TASK_DW = 0, TASK_DA = 1, TASK_Y = 2, TASK_R = 3, TASK_DD = 4, TASK_NONE = 5 };
 
 __device__ __forceinline__ void decode_task(uint32_t t, int T, int& kind, int& I, int& J) {
   kind = TASK_NONE;
@@ -738,12 +738,13 @@ __device__ __forceinline__ void decode_task(uint32_t t, int T, int& kind, int& I
   if (t == 0) { kind = TASK_DW; return; }
   t -= 1;
   for (int g = 0; g < T; ++g) {
-    const uint32_t da = (g >= 1 && g + 1 <= T - 1) ? 1u : 0u;
+    const uint32_t da = (g >= 1 && g + 1 <= T - 1) ? 2u : 0u;
     const uint32_t nr = (uint32_t)max(0, T - g - 2);
     if (t < da + 1 + nr) {
       if (da) {
         if (t == 0) { kind = TASK_DA; I = J = g + 1; return; }
-        t -= 1;
+        if (t == 1) { kind = TASK_DD; I = J = g + 1; return; }
+        t -= 2;
       }
       if (t == 0) { kind = TASK_Y; I = J = g; return; }
       kind = TASK_R; J = g; I = g + 2 + (int)(t - 1);
@@ -754,7 +755,7 @@ __device__ __forceinline__ void decode_task(uint32_t t, int T, int& kind, int& I
 }
 
 __host__ __device__ inline uint32_t chol_tasks(int T) {
-  const int da = T >= 2 ? T - 2 : 0;
+  const int da = T >= 2 ? 2 * (T - 2) : 0;
   const int nr = T >= 2 ? (T - 2) * (T - 1) / 2 : 0;
   return (uint32_t)(1 + T + da + nr);
 }
@@ -873,6 +874,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
               if (ok) ok = tagged_add16(tagged_slots(part_raw, st, 1), seq, accd, sync, status);
             } else {
               if (ok) ok = wait_flag(daflags + st, sync, status);
+              if (ok) ok = wait_flag(daflags + T + st, sync, status);
               const R* ps = part_ptr(st, 0);
               const R* pd = part_ptr(st, 1);
 #pragma unroll
@@ -928,32 +930,30 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
         Xprev = Xcur;
         Xcur = tmp;
       }
-    } else if (kind == TASK_DA) {
-      const int s = I;
-      acc_t accs[2][2], accd[2][2];
+    } else if (kind == TASK_DA || kind == TASK_DD) {
+      // one of the worker's two look-ahead partial sums for step s: the subdiagonal one
+      // (DA, -sum_{K<s-1} L_sK L_{s-1,K}^T) or the diagonal one (DD, -sum_{K<s-1} L_sK L_sK^T),
+      // each a task of its own so that each runs one product per K
+      const int s = I, which = kind == TASK_DA ? 0 : 1;
+      acc_t accp[2][2], dummy[2][2];
 #pragma unroll
       for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-        for (int bj = 0; bj < 2; ++bj) accs[bi][bj] = accd[bi][bj] = acc_t{0, 0, 0, 0};
-      ok = accumulate<R, true>(accs, accd, Lt, T, s, s - 1, s - 1, lds, sync, flags, status, qr, qc,
-                               part_raw, seq);
+        for (int bj = 0; bj < 2; ++bj) accp[bi][bj] = acc_t{0, 0, 0, 0};
+      ok = accumulate<R, false>(accp, dummy, Lt, T, s, which ? s : s - 1, s - 1, lds, sync, flags,
+                                status, qr, qc, part_raw, seq);
       if constexpr (sizeof(R) == 4) {
-        tagged_put16(tagged_slots(part_raw, s, 0), seq, accs);
-        tagged_put16(tagged_slots(part_raw, s, 1), seq, accd);
+        tagged_put16(tagged_slots(part_raw, s, which), seq, accp);
         __syncthreads();
       } else {
-        R* ps = part_ptr(s, 0);
-        R* pd = part_ptr(s, 1);
+        R* pp = part_ptr(s, which);
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
           for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              ps[(bi * 2 + bj) * 4 + v] = accs[bi][bj][v];
-              pd[(bi * 2 + bj) * 4 + v] = accd[bi][bj][v];
-            }
-        publish(daflags + s);
+            for (int v = 0; v < 4; ++v) pp[(bi * 2 + bj) * 4 + v] = accp[bi][bj][v];
+        publish(daflags + which * T + s);
         __syncthreads();
       }
     } else if (kind == TASK_R) {
@@ -1046,7 +1046,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
     }
   }
   // FP32: the last workgroup out also restores kEmpty in the y messages
-  exit_and_reset(sync, flags, (int)(ntile_flags + (uint32_t)T), yflags, yflags ? T : 0,
+  exit_and_reset(sync, flags, (int)(ntile_flags + 2u * (uint32_t)T), yflags, yflags ? T : 0,
                  sizeof(R) == 4 ? y_slots(part_raw, T) : nullptr, sizeof(R) == 4 ? 64 * T : 0);
 }
 

@@ -608,27 +608,34 @@ __device__ __forceinline__ void tagged_put16(uint64_t* p, uint32_t seq,
                            __HIP_MEMORY_SCOPE_AGENT);
       }
 }
-// acc += the 16 values at p once all carry tag seq; false on abort or time-out.
-__device__ bool tagged_add16(const uint64_t* p, uint32_t seq, Mfma<float>::acc_t (&acc)[2][2],
+// acc0 += the 16 values at p0 and acc1 += those at p1 once all 32 carry tag seq (both groups
+// of loads in flight together); false on abort or time-out.
+__device__ bool tagged_add32(const uint64_t* p0, const uint64_t* p1, uint32_t seq,
+                             Mfma<float>::acc_t (&acc0)[2][2], Mfma<float>::acc_t (&acc1)[2][2],
                              SyncArea* sync, int32_t* status) {
   uint32_t spins = 0;
   for (;;) {
-    uint64_t m[16];
+    uint64_t m[32];
 #pragma unroll
-    for (int k = 0; k < 16; ++k)
-      m[k] = __hip_atomic_load(p + k * kThreads + threadIdx.x, __ATOMIC_RELAXED,
+    for (int k = 0; k < 16; ++k) {
+      m[k] = __hip_atomic_load(p0 + k * kThreads + threadIdx.x, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
+      m[16 + k] = __hip_atomic_load(p1 + k * kThreads + threadIdx.x, __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT);
+    }
     bool all = true;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) all &= (uint32_t)(m[k] >> 32) == seq;
+    for (int k = 0; k < 32; ++k) all &= (uint32_t)(m[k] >> 32) == seq;
     if (all) {
 #pragma unroll
       for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
-          for (int v = 0; v < 4; ++v)
-            acc[bi][bj][v] += __uint_as_float((uint32_t)m[(bi * 2 + bj) * 4 + v]);
+          for (int v = 0; v < 4; ++v) {
+            acc0[bi][bj][v] += __uint_as_float((uint32_t)m[(bi * 2 + bj) * 4 + v]);
+            acc1[bi][bj][v] += __uint_as_float((uint32_t)m[16 + (bi * 2 + bj) * 4 + v]);
+          }
       return true;
     }
     if (__hip_atomic_load(&sync->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
@@ -870,8 +877,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
           acc_load_h<R>(accs, Hc, ld, st, st - 1, 0.0, qr, qc);
           if (st >= 2) {
             if constexpr (sizeof(R) == 4) {
-              if (ok) ok = tagged_add16(tagged_slots(part_raw, st, 0), seq, accs, sync, status);
-              if (ok) ok = tagged_add16(tagged_slots(part_raw, st, 1), seq, accd, sync, status);
+              if (ok)
+                ok = tagged_add32(tagged_slots(part_raw, st, 0), tagged_slots(part_raw, st, 1), seq,
+                                  accs, accd, sync, status);
             } else {
               if (ok) ok = wait_flag(daflags + st, sync, status);
               if (ok) ok = wait_flag(daflags + T + st, sync, status);

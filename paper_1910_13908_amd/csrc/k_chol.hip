@@ -341,41 +341,6 @@ __device__ int panel_factor(R* A, R* rdiag) {
   return __any(!(rc > (R)0 && rc < (R)INFINITY)) ? 1 : 0;
 }
 
-// All waves: A[r][c] -= sum_{k in panel P} A[r][k] A[c][k] for the lower 16x16 blocks right
-// of and below panel P.
-template <typename R, int P>
-__device__ void panel_update(R* A) {
-  constexpr int STR = Mfma<R>::STR;
-  constexpr int c0 = 16 * P;
-  constexpr int nb = 3 - P;
-  constexpr int nblk = nb * (nb + 1) / 2;
-  using acc_t = typename Mfma<R>::acc_t;
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, rr = lane & 15;
-  for (int blk = wv; blk < nblk; blk += 4) {
-    int br = P + 1, bc = P + 1, t = blk;
-    while (t > br - (P + 1)) {
-      t -= br - P;
-      ++br;
-    }
-    bc = P + 1 + t;
-    acc_t acc;
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-      acc[v] = A[(16 * br + out_row<R>(lane, v)) * STR + 16 * bc + out_col(lane, v)];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int k = c0 + 4 * g + s;
-      acc = Mfma<R>::mma(-A[(16 * br + rr) * STR + k], A[(16 * bc + rr) * STR + k], acc);
-    }
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-      A[(16 * br + out_row<R>(lane, v)) * STR + 16 * bc + out_col(lane, v)] = acc[v];
-  }
-}
-
-// Factor the tile in A (lower triangle) in place and write X = L^{-1} into X; the blocks of X
-// above its block diagonal must already hold zeros (zero_upper_blocks).  Returns nonzero (in
-// every thread) if a pivot was not positive.
 // Zero the six 16x16 blocks above the block diagonal of a 64x64 LDS tile.
 template <typename R>
 __device__ __forceinline__ void zero_upper_blocks(R* X) {
@@ -391,34 +356,35 @@ __device__ __forceinline__ void zero_upper_blocks(R* X) {
   }
 }
 
+// One wave: A[br][bc] -= A[br][P] A[bc][P]^T for one 16x16 block (the rank-16 update of panel
+// P), with MFMA.
 template <typename R>
-__device__ int cholinv_tile(R* A, R* X, R* rdiag) {
+__device__ __forceinline__ void block_update(R* A, int br, int bc, int P) {
   constexpr int STR = Mfma<R>::STR;
   using acc_t = typename Mfma<R>::acc_t;
-  __shared__ int s_bad;
-  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63, g = lane >> 4, rr = lane & 15;
-  int bad = 0;
-  if (wv == 0) bad |= panel_factor<R, 0>(A, rdiag);
-  __syncthreads();
-  panel_update<R, 0>(A);
-  __syncthreads();
-  if (wv == 0) bad |= panel_factor<R, 1>(A, rdiag);
-  __syncthreads();
-  panel_update<R, 1>(A);
-  __syncthreads();
-  if (wv == 0) bad |= panel_factor<R, 2>(A, rdiag);
-  __syncthreads();
-  panel_update<R, 2>(A);
-  __syncthreads();
-  if (wv == 0) {
-    bad |= panel_factor<R, 3>(A, rdiag);
-    if (lane == 0) s_bad = bad;
+  const int lane = threadIdx.x & 63, g = lane >> 4, rr = lane & 15;
+  acc_t acc;
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+    acc[v] = A[(16 * br + out_row<R>(lane, v)) * STR + 16 * bc + out_col(lane, v)];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int k = 16 * P + 4 * g + s;
+    acc = Mfma<R>::mma(-A[(16 * br + rr) * STR + k], A[(16 * bc + rr) * STR + k], acc);
   }
-  __syncthreads();
-  // inverse of the diagonal 16x16 blocks: wave w takes block w, lane c < 16 column c; the
-  // right-hand side e_c is formed arithmetically (no per-row lane masks)
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+    A[(16 * br + out_row<R>(lane, v)) * STR + 16 * bc + out_col(lane, v)] = acc[v];
+}
+
+// One wave: X_bb = L_bb^{-1} of diagonal 16x16 block b by forward substitution, lane c < 16
+// taking column c; the right-hand side e_c is formed arithmetically (no per-row lane masks).
+template <typename R>
+__device__ __forceinline__ void diag_inverse(const R* A, R* X, const R* rdiag, int b) {
+  constexpr int STR = Mfma<R>::STR;
+  const int lane = threadIdx.x & 63;
   if (lane < 16) {
-    const int b0 = 16 * wv, c = lane;
+    const int b0 = 16 * b, c = lane;
     R x[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
@@ -435,29 +401,92 @@ __device__ int cholinv_tile(R* A, R* X, R* rdiag) {
 #pragma unroll
     for (int i = 0; i < 16; ++i) X[(b0 + i) * STR + b0 + c] = x[i];
   }
-  __syncthreads();
-  // off-diagonal blocks, one block row at a time: X_ij = -X_ii sum_{k=j}^{i-1} L_ik X_kj
-  for (int i = 1; i < 4; ++i) {
-    const int j = wv;
-    if (j < i) {
-      acc_t t = acc_t{0, 0, 0, 0};
-      for (int k = j; k < i; ++k) {
+}
+
+// One wave: X_ij = -X_ii sum_{k=j}^{i-1} L_ik X_kj (i > j), with MFMA.
+template <typename R>
+__device__ __forceinline__ void offdiag_inverse(const R* A, R* X, int i, int j) {
+  constexpr int STR = Mfma<R>::STR;
+  using acc_t = typename Mfma<R>::acc_t;
+  const int lane = threadIdx.x & 63, g = lane >> 4, rr = lane & 15;
+  acc_t t = acc_t{0, 0, 0, 0};
+  for (int k = j; k < i; ++k) {
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const int m = kwalk16<R>(g, s);
-          t = Mfma<R>::mma(A[(16 * i + rr) * STR + 16 * k + m], X[(16 * k + m) * STR + 16 * j + rr], t);
-        }
-      }
-      acc_t o = acc_t{0, 0, 0, 0};
-#pragma unroll
-      for (int s = 0; s < 4; ++s)
-        o = Mfma<R>::mma(-X[(16 * i + rr) * STR + 16 * i + kwalk16<R>(g, s)], t[s], o);
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-        X[(16 * i + out_row<R>(lane, v)) * STR + 16 * j + out_col(lane, v)] = o[v];
+    for (int s = 0; s < 4; ++s) {
+      const int m = kwalk16<R>(g, s);
+      t = Mfma<R>::mma(A[(16 * i + rr) * STR + 16 * k + m], X[(16 * k + m) * STR + 16 * j + rr], t);
     }
-    __syncthreads();
   }
+  acc_t o = acc_t{0, 0, 0, 0};
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+    o = Mfma<R>::mma(-X[(16 * i + rr) * STR + 16 * i + kwalk16<R>(g, s)], t[s], o);
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+    X[(16 * i + out_row<R>(lane, v)) * STR + 16 * j + out_col(lane, v)] = o[v];
+}
+
+// Factor the tile in A (lower triangle) in place and write X = L^{-1} into X; the blocks of X
+// above its block diagonal must already hold zeros (zero_upper_blocks).  Returns nonzero (in
+// every thread) if a pivot was not positive.  Six phases, one workgroup barrier each: wave 0
+// runs the chain (the part of the previous panel's update that the next panel needs, then that
+// panel's factorisation), while waves 1-3 apply the rest of the update and form the inverse
+// blocks whose operands are final:
+//   1: w0 U0 on panel 1, P1 | w1 U0 on (2,2),(3,2) | w2 U0 on (3,3) | w3 X_00
+//   2: w0 U1 on panel 2, P2 | w1 U1 on (3,3)       | w2 X_11
+//   3: w0 U2 on panel 3, P3 | w1 X_22              | w2 X_10
+//   4: w0 X_33              | w1 X_20              | w2 X_21
+//   5: w0 X_30              | w1 X_31              | w2 X_32
+template <typename R>
+__device__ int cholinv_tile(R* A, R* X, R* rdiag) {
+  __shared__ int s_bad;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int bad = 0;
+  if (wv == 0) bad |= panel_factor<R, 0>(A, rdiag);
+  __syncthreads();
+  if (wv == 0) {
+    block_update<R>(A, 1, 1, 0);
+    block_update<R>(A, 2, 1, 0);
+    block_update<R>(A, 3, 1, 0);
+    wave_sync_lds();
+    bad |= panel_factor<R, 1>(A, rdiag);
+  } else if (wv == 1) {
+    block_update<R>(A, 2, 2, 0);
+    block_update<R>(A, 3, 2, 0);
+  } else if (wv == 2) {
+    block_update<R>(A, 3, 3, 0);
+  } else {
+    diag_inverse<R>(A, X, rdiag, 0);
+  }
+  __syncthreads();
+  if (wv == 0) {
+    block_update<R>(A, 2, 2, 1);
+    block_update<R>(A, 3, 2, 1);
+    wave_sync_lds();
+    bad |= panel_factor<R, 2>(A, rdiag);
+  } else if (wv == 1) {
+    block_update<R>(A, 3, 3, 1);
+  } else if (wv == 2) {
+    diag_inverse<R>(A, X, rdiag, 1);
+  }
+  __syncthreads();
+  if (wv == 0) {
+    block_update<R>(A, 3, 3, 2);
+    wave_sync_lds();
+    bad |= panel_factor<R, 3>(A, rdiag);
+    if (lane == 0) s_bad = bad;
+  } else if (wv == 1) {
+    diag_inverse<R>(A, X, rdiag, 2);
+  } else if (wv == 2) {
+    offdiag_inverse<R>(A, X, 1, 0);
+  }
+  __syncthreads();
+  if (wv == 0) diag_inverse<R>(A, X, rdiag, 3);
+  else if (wv == 1) offdiag_inverse<R>(A, X, 2, 0);
+  else if (wv == 2) offdiag_inverse<R>(A, X, 2, 1);
+  __syncthreads();
+  if (wv < 3) offdiag_inverse<R>(A, X, 3, wv);
+  __syncthreads();
   return s_bad;
 }
 

@@ -226,7 +226,7 @@ ddc_status obs_dev(ddc_ctx* c, const ddc_obs* o, ObsDev& d) {
 struct SolveBufs {
   int n, n_pad, T, ld;
   void *Hc, *Lt, *Linv, *part, *cpart, *LtT, *LinvT;
-  double *g, *diag, *d, *y, *s, *e, *cost_part, *s_part, *scalar, *prow, *pcol;
+  double *g, *diag, *d, *y, *s, *e, *cost_part, *scalar, *prow, *pcol;
   size_t h_off;
 };
 
@@ -244,7 +244,6 @@ void layout_solve(Bump& bp, SolveBufs& b, int n, size_t es, int64_t B, int64_t n
   offs.push_back(bp.take((size_t)kPartials * (B > 0 ? B : 1) * es));   // part
   for (int i = 0; i < 6; ++i) offs.push_back(bp.take(np * sizeof(double)));  // g diag d y s e
   offs.push_back(bp.take((size_t)(nblk_max > 0 ? nblk_max : 1) * sizeof(double)));  // cost_part
-  offs.push_back(bp.take((size_t)b.T * sizeof(double)));                // s_part
   offs.push_back(bp.take(64 * sizeof(double)));                         // scalars
   const size_t ntiles = (size_t)b.T * (b.T + 1) / 2;
   offs.push_back(bp.take(ntiles * 64 * sizeof(double)));               // prow
@@ -269,18 +268,17 @@ void bind_solve(ddc_ctx* c, SolveBufs& b, const std::vector<size_t>& o) {
   b.s = reinterpret_cast<double*>(w + o[8]);
   b.e = reinterpret_cast<double*>(w + o[9]);
   b.cost_part = reinterpret_cast<double*>(w + o[10]);
-  b.s_part = reinterpret_cast<double*>(w + o[11]);
-  b.scalar = reinterpret_cast<double*>(w + o[12]);
-  b.prow = reinterpret_cast<double*>(w + o[13]);
-  b.pcol = reinterpret_cast<double*>(w + o[14]);
-  b.cpart = w + o[15];
+  b.scalar = reinterpret_cast<double*>(w + o[11]);
+  b.prow = reinterpret_cast<double*>(w + o[12]);
+  b.pcol = reinterpret_cast<double*>(w + o[13]);
+  b.cpart = w + o[14];
   // the factorisation's FP32 tagged messages carry nonzero tags (zeroed scratch holds none);
   // its y messages start empty
   const size_t ntag = (size_t)b.T * 2 * 4096 + (size_t)b.T * (b.T + 1) / 2 * 4096;
   (void)hipMemsetAsync(b.cpart, 0, ntag * 8, c->stream);
   (void)launch_fill_empty(reinterpret_cast<uint64_t*>(b.cpart) + ntag, 64 * b.T, c->stream);
-  b.LtT = w + o[16];
-  b.LinvT = w + o[17];
+  b.LtT = w + o[15];
+  b.LinvT = w + o[16];
   b.h_off = o[0];
 }
 

@@ -13,20 +13,28 @@
 // diagonal tile in turn) with its operands in LDS, so the dependent chain along the
 // diagonal never waits on another workgroup; the others pre-accumulate what it needs and
 // fill in the rest of the factor.  With a right-hand side g the same kernel also runs the
-// forward substitution y = L^{-1} g block by block as the factor appears.  Results publish
-// ready flags; every wait is on work that is finished or held by a running workgroup.  Tickets are claimed only by running workgroups, so the smallest
-// unfinished ticket never waits on unfinished work and the schedule cannot deadlock without
-// any co-residency guarantee.  Every wait is bounded; on expiry the kernel raises an abort
-// flag, every other wait returns at once, and the status word reports DDC_ETIMEOUT.  The
-// last workgroup to leave resets the tickets and flags, so the kernel needs no host-side
-// clearing between launches.
+// forward substitution y = L^{-1} g block by block as the factor appears.  Every wait is on
+// work that is finished or held by a running workgroup: tickets are claimed only by running
+// workgroups, so the smallest unfinished ticket never waits on unfinished work and the
+// schedule cannot deadlock without any co-residency guarantee.  Every wait is bounded; on
+// expiry the kernel raises an abort flag, every other wait returns at once, and the status
+// word reports DDC_ETIMEOUT.
+//
+// Hand-offs between workgroups.  An agent-scope release/acquire pair writes back and
+// invalidates the L2 of the XCDs involved, which dominated the kernel's time, so the FP32
+// factorisation has none: every tile a task hands over is also written as a tagged copy (each
+// 64-bit slot holds the value and the launch's sequence number) that consumers poll until
+// every tag they read matches, and the forward solve passes its blocks as messages that hold
+// an "empty" pattern until written.  FP64 values leave no room for a tag: there results
+// publish ready flags with release/acquire.  The last workgroup to leave resets the tickets,
+// flags and messages, so the kernel needs no host-side clearing between launches.
 //
 // The factor is stored tile-packed (column-major over the tiles of the lower triangle,
 // row-major inside a tile) next to the inverses of the diagonal tiles, which the
-// triangular solves use as small dense products.  Forward and backward substitution follow
-// the same ticket-and-flag scheme over 64-row blocks.  In mixed precision the factor and
-// the products run in FP32 (FP32 MFMA); right-hand sides, solutions and the refinement
-// residual g - (H + mu I) d are FP64.
+// triangular solves use as small dense products.  Forward and backward substitution use the
+// same ticket scheme over 64-row blocks, with message hand-offs.  In mixed precision the
+// factor and the products run in FP32 (FP32 MFMA); right-hand sides, solutions and the
+// refinement residual g - (H + mu I) d are FP64.
 #include "common.h"
 
 #include <type_traits>

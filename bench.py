@@ -382,7 +382,9 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    ctx.enable_timing(True)
+    # the timed steps bracket only the kernels reported from them (the factorisation for the
+    # roofline, the predict): every event pair adds a stream marker that waits for its launch
+    ctx.enable_timing(True, timers=[dd.TIMER_CHOLESKY, dd.TIMER_PREDICT])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -390,11 +392,17 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
-    timers = {name: ctx.timing(i) for i, name in enumerate(
-        ["cholesky", "predict", "build", "trsv", "trial", "model", "refine", "adjoint"])}
-    ctx.enable_timing(False)
+    timer_names = ["cholesky", "predict", "build", "trsv", "trial", "model", "refine", "adjoint"]
+    timers = {name: ctx.timing(i) for i, name in enumerate(timer_names)}
+    # one more step with every kernel class timed: the per-kernel breakdown, and the LM info
+    ctx.enable_timing(True)
+    torch.cuda.synchronize()
+    tb0 = time.perf_counter()
     infos = step(want_info=True)
     torch.cuda.synchronize()
+    elapsed_b = time.perf_counter() - tb0
+    breakdown = {name: ctx.timing(i) for i, name in enumerate(timer_names)}
+    ctx.enable_timing(False)
     final_cost = infos[-1][-1].cost if infos else None   # residual cost after the last visit
 
     ms_per_step = 1e3 * elapsed / args.steps
@@ -406,9 +414,9 @@ def main():
     vis_per_predict = K * ob.B * ob.T * ob.F
     gvis = (n_pr * vis_per_predict) / (ms_pr * 1e-3) / 1e9 if ms_pr > 0 else 0.0
     kernel_ms = {k: {"launches": v[0], "avg_us": 1e3 * v[1] / max(v[0], 1),
-                     "share_of_step": v[1] / (1e3 * elapsed) if elapsed > 0 else 0.0}
-                 for k, v in timers.items()}
-    n_tr, ms_tr, by_tr = timers["trial"]
+                     "share_of_step": v[1] / (1e3 * elapsed_b) if elapsed_b > 0 else 0.0}
+                 for k, v in breakdown.items()}
+    n_tr, ms_tr, by_tr = breakdown["trial"]
 
     out = {
         "metric": "LM iters/s", "value": value, "unit": "LM iters/s", "n_gpus": 1,
@@ -436,6 +444,8 @@ def main():
         # so its average over launches would not be a bandwidth)
         "roofline_hbm": _hbm_roofline("k_trial_cost", n_tr, ms_tr, by_tr),
         "kernels": kernel_ms,
+        "kernels_note": "per-kernel HIP-event times from one extra step with every kernel class "
+                        "timed (the timed steps time only the factorisation and the predict)",
         "final_total_cost": final_cost,
     }
 

@@ -263,6 +263,11 @@ typedef enum {
   DDC_TIMER_PREDICT_FACTORED = 8  /* station-factorised predict; work = coherencies (K*T*F*B) */
 } ddc_timer;
 ddc_status ddc_enable_timing(ddc_ctx* ctx, int32_t on);
+/* Time only the kernel classes whose bit (1 << ddc_timer) is set in mask (0: none).  Each
+ * bracketing event pair adds a stream marker that waits for the launch before it, so a
+ * throughput measurement times only the kernels it reports.  Resets the totals like
+ * ddc_enable_timing. */
+ddc_status ddc_enable_timers(ddc_ctx* ctx, uint32_t mask);
 ddc_status ddc_get_timing(ddc_ctx* ctx, int32_t which, int64_t* launches, double* total_ms,
                           double* total_work);
 

@@ -51,7 +51,7 @@ struct ddc_ctx {
   int32_t* ant = nullptr;        // [2][B] canonical baseline table
   const void* h_ptr = nullptr;   // matrix storage initialised for (address, n_pad, n, elem size)
   int h_npad = -1, h_n = -1, h_es = -1;
-  bool timing = false;
+  uint32_t timing = 0u;          // bit k set: launches of timer k are bracketed with events
   std::vector<Pending> pending;
   std::vector<hipEvent_t> pool;
   TimerAcc acc[T_COUNT];
@@ -109,13 +109,14 @@ hipEvent_t get_event(ddc_ctx* c) {
 template <typename F>
 ddc_status timed(ddc_ctx* c, int which, double work, F&& launch) {
   hipEvent_t a = nullptr, b = nullptr;
-  if (c->timing) {
+  const bool on = (c->timing >> which) & 1u;
+  if (on) {
     a = get_event(c);
     b = get_event(c);
     if (a) HIPCK(hipEventRecord(a, c->stream));
   }
   HIPCK(launch());
-  if (c->timing && a && b) {
+  if (on && a && b) {
     HIPCK(hipEventRecord(b, c->stream));
     c->pending.push_back({which, a, b, work});
   }
@@ -980,12 +981,16 @@ ddc_status ddc_cost_gradient(ddc_ctx* c, const ddc_obs* obs, int32_t K, const vo
   return cost_gradient_impl<double>(c, o, K, vis, coh, jones, grad, cost);
 }
 
-ddc_status ddc_enable_timing(ddc_ctx* c, int32_t on) {
+ddc_status ddc_enable_timers(ddc_ctx* c, uint32_t mask) {
   if (!c) return DDC_EINVAL;
   DDCCK(collect_timing(c));
-  c->timing = on != 0;
+  c->timing = mask;
   for (auto& a : c->acc) a = TimerAcc();
   return DDC_OK;
+}
+
+ddc_status ddc_enable_timing(ddc_ctx* c, int32_t on) {
+  return ddc_enable_timers(c, on ? 0xffffffffu : 0u);
 }
 
 ddc_status ddc_get_timing(ddc_ctx* c, int32_t which, int64_t* launches, double* total_ms,

@@ -34,7 +34,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ENOTPD, ENONFINITE, ETIMEOUT = 0, -1, -2, -3, -4, -
 EXPORTS = ("ddc_default_lm_opts", "ddc_create", "ddc_destroy", "ddc_set_stream", "ddc_last_error",
            "ddc_workspace_bytes", "ddc_predict", "ddc_predict_factored", "ddc_residual", "ddc_add_model",
            "ddc_build_normal_eq", "ddc_damped_solve", "ddc_lm_solve", "ddc_calibrate",
-           "ddc_cost_gradient", "ddc_enable_timing", "ddc_get_timing", "ddc_calibrate_footprint",
+           "ddc_cost_gradient", "ddc_enable_timing", "ddc_enable_timers", "ddc_get_timing", "ddc_calibrate_footprint",
            "ddc_server_create", "ddc_server_destroy", "ddc_server_submit", "ddc_server_wait",
            "ddc_server_stats", "ddc_server_last_error")
 
@@ -99,6 +99,7 @@ _lib.ddc_calibrate.argtypes = [_vp, ct.POINTER(Obs), ct.POINTER(Sky), _vp, _vp, 
 _lib.ddc_cost_gradient.argtypes = [_vp, ct.POINTER(Obs), ct.c_int32, _vp, _vp, _vp, ct.c_int32, _vp,
                                    ct.POINTER(ct.c_double)]
 _lib.ddc_enable_timing.argtypes = [_vp, ct.c_int32]
+_lib.ddc_enable_timers.argtypes = [_vp, ct.c_uint32]
 _lib.ddc_get_timing.argtypes = [_vp, ct.c_int32, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_double),
                                 ct.POINTER(ct.c_double)]
 _lib.ddc_calibrate_footprint.argtypes = [ct.POINTER(Obs), ct.c_int32, ct.c_int32, ct.c_int32]
@@ -266,8 +267,15 @@ class Context:
                                            precision, _ptr(grad), ct.byref(cost) if want_cost else None))
         return (cost.value if want_cost else None), grad
 
-    def enable_timing(self, on=True):
-        self._check(_lib.ddc_enable_timing(self.h, 1 if on else 0))
+    def enable_timing(self, on=True, timers=None):
+        """Time every kernel class (on), none, or only those listed in timers (TIMER_*)."""
+        if timers is None:
+            self._check(_lib.ddc_enable_timing(self.h, 1 if on else 0))
+        else:
+            mask = 0
+            for t in timers:
+                mask |= 1 << t
+            self._check(_lib.ddc_enable_timers(self.h, mask if on else 0))
 
     def timing(self, which):
         n = ct.c_int64(0)

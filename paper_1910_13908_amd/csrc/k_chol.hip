@@ -624,7 +624,7 @@ __device__ bool msg_get16(const uint64_t* p, F off, double (&v)[16], SyncArea* s
   }
 }
 
-// Look-ahead partial sums in FP32 travel as tagged messages: each 64-bit slot holds a value and
+// Look-ahead tiles in FP32 travel as tagged messages: each 64-bit slot holds a value and
 // the launch's sequence number, so the diagonal worker reads them as soon as they exist, with
 // no flag, no fence and no clearing between launches.  Slot (tile s, which, k, thread) sits at
 // ((s * 2 + which) * 16 + k) * kThreads + thread, so a wave's accesses are contiguous.
@@ -645,9 +645,9 @@ __device__ __forceinline__ void tagged_put16(uint64_t* p, uint32_t seq,
                            __HIP_MEMORY_SCOPE_AGENT);
       }
 }
-// acc0 += the 16 values at p0 and acc1 += those at p1 once all 32 carry tag seq (both groups
+// acc0 = the 16 values at p0 and acc1 = those at p1 once all 32 carry tag seq (both groups
 // of loads in flight together); false on abort or time-out.
-__device__ bool tagged_add32(const uint64_t* p0, const uint64_t* p1, uint32_t seq,
+__device__ bool tagged_get32(const uint64_t* p0, const uint64_t* p1, uint32_t seq,
                              Mfma<float>::acc_t (&acc0)[2][2], Mfma<float>::acc_t (&acc1)[2][2],
                              SyncArea* sync, int32_t* status) {
   uint32_t spins = 0;
@@ -670,8 +670,8 @@ __device__ bool tagged_add32(const uint64_t* p0, const uint64_t* p1, uint32_t se
         for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            acc0[bi][bj][v] += __uint_as_float((uint32_t)m[(bi * 2 + bj) * 4 + v]);
-            acc1[bi][bj][v] += __uint_as_float((uint32_t)m[16 + (bi * 2 + bj) * 4 + v]);
+            acc0[bi][bj][v] = __uint_as_float((uint32_t)m[(bi * 2 + bj) * 4 + v]);
+            acc1[bi][bj][v] = __uint_as_float((uint32_t)m[16 + (bi * 2 + bj) * 4 + v]);
           }
       return true;
     }
@@ -767,8 +767,9 @@ __device__ __forceinline__ bool tagged_tile_fetch(const uint64_t* t, uint32_t se
 // At step s it computes the subdiagonal tile L_{s,s-1} = A_{s,s-1} X_{s-1}^T, applies its
 // rank-64 update to the diagonal tile and factors/inverts it.  Every other workgroup takes
 // tickets >= 1 in groups g = 0..T-1:
-//   DA_{g+1} (2 <= g+1 <= T-1): the partial sums -sum_{K <= g-1} L_{g+1,K} L_{g,K}^T and
-//            -sum_{K <= g-1} L_{g+1,K} L_{g+1,K}^T that the DW adds at step g+1;
+//   DA_{g+1}, DD_{g+1} (2 <= g+1 <= T-1): the tiles the DW starts step g+1 from, all but its
+//            last product: A_{g+1,g} - sum_{K <= g-1} L_{g+1,K} L_{g,K}^T (DA) and
+//            A_{g+1,g+1} + mu I - sum_{K <= g-1} L_{g+1,K} L_{g+1,K}^T (DD);
 //   Y_g:     forward-substitution block y_g = X_gg (g_g - sum_{K<g} L_gK y_K);
 //   R_g:     tiles (I, g), I >= g+2: A_Ig - sum_K L_IK L_gK^T, then times X_gg^T.
 // A task waits only on tasks of earlier groups or on DW steps whose own inputs come from
@@ -908,15 +909,17 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
       zero_upper_blocks<R>(Xcur);
       for (int st = 0; st < T; ++st) {
         acc_t accd[2][2];
-        acc_load_h<R>(accd, Hc, ld, st, st, mu, qr, qc);
+        if (st < 2) acc_load_h<R>(accd, Hc, ld, st, st, mu, qr, qc);
         if (st >= 1) {
           acc_t accs[2][2];
-          acc_load_h<R>(accs, Hc, ld, st, st - 1, 0.0, qr, qc);
-          if (st >= 2) {
+          if (st < 2) {
+            acc_load_h<R>(accs, Hc, ld, st, st - 1, 0.0, qr, qc);
+          } else {
+            // from step 2 on the look-ahead tasks deliver both tiles with H already added
             if constexpr (sizeof(R) == 4) {
               if (ok)
-                ok = tagged_add32(tagged_slots(part_raw, st, 0), tagged_slots(part_raw, st, 1), seq,
-                                  accs, accd, sync, status);
+                ok = tagged_get32(tagged_slots(part_raw, st, 0), tagged_slots(part_raw, st, 1),
+                                  seq, accs, accd, sync, status);
             } else {
               if (ok) ok = wait_flag(daflags + st, sync, status);
               if (ok) ok = wait_flag(daflags + T + st, sync, status);
@@ -928,8 +931,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
                 for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
                   for (int v = 0; v < 4; ++v) {
-                    accs[bi][bj][v] += ps[(bi * 2 + bj) * 4 + v];
-                    accd[bi][bj][v] += pd[(bi * 2 + bj) * 4 + v];
+                    accs[bi][bj][v] = ps[(bi * 2 + bj) * 4 + v];
+                    accd[bi][bj][v] = pd[(bi * 2 + bj) * 4 + v];
                   }
             }
           }
@@ -976,9 +979,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
         Xcur = tmp;
       }
     } else if (kind == TASK_DA || kind == TASK_DD) {
-      // one of the worker's two look-ahead partial sums for step s: the subdiagonal one
-      // (DA, -sum_{K<s-1} L_sK L_{s-1,K}^T) or the diagonal one (DD, -sum_{K<s-1} L_sK L_sK^T),
-      // each a task of its own so that each runs one product per K
+      // one of the worker's two look-ahead tiles for step s: the subdiagonal one
+      // (DA, -sum_{K<s-1} L_sK L_{s-1,K}^T + H_{s,s-1}) or the diagonal one
+      // (DD, -sum_{K<s-1} L_sK L_sK^T + H_ss + mu I), each a task of its own so that each runs
+      // one product per K
       const int s = I, which = kind == TASK_DA ? 0 : 1;
       acc_t accp[2][2], dummy[2][2];
 #pragma unroll
@@ -987,6 +991,18 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
         for (int bj = 0; bj < 2; ++bj) accp[bi][bj] = acc_t{0, 0, 0, 0};
       ok = accumulate<R, false>(accp, dummy, Lt, T, s, which ? s : s - 1, s - 1, lds, sync, flags,
                                 status, qr, qc, part_raw, seq);
+      {
+        // the H tile (with the damping on the diagonal) is added here, after the products
+        // and off the worker's path; the sum rounds as the worker's own (H + mu I) + partial
+        acc_t hp[2][2];
+        acc_load_h<R>(hp, Hc, ld, s, which ? s : s - 1, which ? mu : 0.0, qr, qc);
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) accp[bi][bj][v] += hp[bi][bj][v];
+      }
       if constexpr (sizeof(R) == 4) {
         tagged_put16(tagged_slots(part_raw, s, which), seq, accp);
         __syncthreads();

@@ -645,36 +645,38 @@ __device__ __forceinline__ void tagged_put16(uint64_t* p, uint32_t seq,
                            __HIP_MEMORY_SCOPE_AGENT);
       }
 }
-// acc0 = the 16 values at p0 and acc1 = those at p1 once all 32 carry tag seq (both groups
-// of loads in flight together); false on abort or time-out.
-__device__ bool tagged_get32(const uint64_t* p0, const uint64_t* p1, uint32_t seq,
-                             Mfma<float>::acc_t (&acc0)[2][2], Mfma<float>::acc_t (&acc1)[2][2],
-                             SyncArea* sync, int32_t* status) {
+// One look-ahead tile: its 16 loads per thread are issued without waiting (tagged_issue16) and
+// the values taken once every tag matches (tagged_take16); tagged_poll16 is the bounded wait.
+// Keeping issue and use apart lets the loads stay in flight over other work.
+__device__ __forceinline__ void tagged_issue16(const uint64_t* p, uint64_t (&m)[16]) {
+#pragma unroll
+  for (int k = 0; k < 16; ++k)
+    m[k] = __hip_atomic_load(p + k * kThreads + threadIdx.x, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ bool tagged_take16(const uint64_t (&m)[16], uint32_t seq,
+                                              Mfma<float>::acc_t (&acc)[2][2]) {
+  bool all = true;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) all &= (uint32_t)(m[k] >> 32) == seq;
+  if (!all) return false;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        acc[bi][bj][v] = __uint_as_float((uint32_t)m[(bi * 2 + bj) * 4 + v]);
+  return true;
+}
+// false on abort or time-out
+__device__ bool tagged_poll16(const uint64_t* p, uint32_t seq, Mfma<float>::acc_t (&acc)[2][2],
+                              SyncArea* sync, int32_t* status) {
   uint32_t spins = 0;
   for (;;) {
-    uint64_t m[32];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      m[k] = __hip_atomic_load(p0 + k * kThreads + threadIdx.x, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-      m[16 + k] = __hip_atomic_load(p1 + k * kThreads + threadIdx.x, __ATOMIC_RELAXED,
-                                    __HIP_MEMORY_SCOPE_AGENT);
-    }
-    bool all = true;
-#pragma unroll
-    for (int k = 0; k < 32; ++k) all &= (uint32_t)(m[k] >> 32) == seq;
-    if (all) {
-#pragma unroll
-      for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            acc0[bi][bj][v] = __uint_as_float((uint32_t)m[(bi * 2 + bj) * 4 + v]);
-            acc1[bi][bj][v] = __uint_as_float((uint32_t)m[16 + (bi * 2 + bj) * 4 + v]);
-          }
-      return true;
-    }
+    uint64_t m[16];
+    tagged_issue16(p, m);
+    if (tagged_take16(m, seq, acc)) return true;
     if (__hip_atomic_load(&sync->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
       return false;
     if (++spins > kSpinLimit) {
@@ -908,18 +910,27 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
       zero_upper_blocks<R>(Xprev);
       zero_upper_blocks<R>(Xcur);
       for (int st = 0; st < T; ++st) {
-        acc_t accd[2][2];
-        if (st < 2) acc_load_h<R>(accd, Hc, ld, st, st, mu, qr, qc);
+        // Steps 0 and 1 start from H; later steps from the two look-ahead tiles (H already
+        // added).  The H loads come first and, in FP32, both tiles' loads are issued on every
+        // step (the slots of steps 0 and 1 exist and go unused), so that on every path these 32
+        // loads are the youngest in flight: the in-order memory-counter waits then leave the
+        // diagonal tile's 16 loads in flight over the subdiagonal product and the diagonal
+        // update, which need only the subdiagonal tile.
+        acc_t accd[2][2], accs[2][2];
+        if (st < 2) {
+          acc_load_h<R>(accd, Hc, ld, st, st, mu, qr, qc);
+          if (st == 1) acc_load_h<R>(accs, Hc, ld, st, st - 1, 0.0, qr, qc);
+        }
+        uint64_t mda[16], mdd[16];
+        if constexpr (sizeof(R) == 4) {
+          tagged_issue16(tagged_slots(part_raw, st, 0), mda);
+          tagged_issue16(tagged_slots(part_raw, st, 1), mdd);
+        }
         if (st >= 1) {
-          acc_t accs[2][2];
-          if (st < 2) {
-            acc_load_h<R>(accs, Hc, ld, st, st - 1, 0.0, qr, qc);
-          } else {
-            // from step 2 on the look-ahead tasks deliver both tiles with H already added
+          if (st >= 2) {
             if constexpr (sizeof(R) == 4) {
-              if (ok)
-                ok = tagged_get32(tagged_slots(part_raw, st, 0), tagged_slots(part_raw, st, 1),
-                                  seq, accs, accd, sync, status);
+              if (ok && !tagged_take16(mda, seq, accs))
+                ok = tagged_poll16(tagged_slots(part_raw, st, 0), seq, accs, sync, status);
             } else {
               if (ok) ok = wait_flag(daflags + st, sync, status);
               if (ok) ok = wait_flag(daflags + T + st, sync, status);
@@ -953,7 +964,28 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
             publish(flags + tile_index(st, st - 1, T));
           }
           __syncthreads();
-          tile_mma<R, true>(accd, Lbuf, Lbuf, qr, qc);
+          if (sizeof(R) == 4 && st >= 2) {
+            // the diagonal update runs from zero and the diagonal look-ahead tile is added
+            // after it, so its loads are waited for only here
+            acc_t upd[2][2];
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+              for (int bj = 0; bj < 2; ++bj) upd[bi][bj] = acc_t{0, 0, 0, 0};
+            tile_mma<R, true>(upd, Lbuf, Lbuf, qr, qc);
+            if constexpr (sizeof(R) == 4) {
+              if (ok && !tagged_take16(mdd, seq, accd))
+                ok = tagged_poll16(tagged_slots(part_raw, st, 1), seq, accd, sync, status);
+            }
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+              for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) accd[bi][bj][v] += upd[bi][bj][v];
+          } else {
+            tile_mma<R, true>(accd, Lbuf, Lbuf, qr, qc);
+          }
           __syncthreads();
         }
         acc_to_lds<R>(accd, Abuf, qr, qc);

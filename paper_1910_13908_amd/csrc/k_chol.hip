@@ -1535,14 +1535,31 @@ __global__ __launch_bounds__(kThreads) void k_symv_combine(
   __shared__ double sh[kThreads];
   const int B = blockIdx.x;           // block row
   const int tid = threadIdx.x, r = tid & 63, part = tid >> 6;
-  // block row B gathers prow of tiles (B, J), J <= B, and pcol of tiles (I, B), I > B
+  // block row B gathers prow of tiles (B, J), J <= B, and pcol of tiles (I, B), I > B; each
+  // thread takes every fourth one, eight loads in flight at a time, added in a fixed order
   double acc = 0.0;
-  for (int J = part; J <= B; J += 4) {
-    const uint32_t ti = (uint32_t)(J * T - (J * (J - 1)) / 2 + (B - J));
-    acc += prow[(int64_t)ti * 64 + r];
+  for (int J0 = part; J0 <= B; J0 += 32) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int J = J0 + 4 * u;
+      const uint32_t ti = (uint32_t)(J * T - (J * (J - 1)) / 2 + (B - J));
+      v[u] = J <= B ? prow[(int64_t)ti * 64 + r] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += v[u];
   }
   const uint32_t cstart = (uint32_t)(B * T - (B * (B - 1)) / 2);
-  for (int I = B + 1 + part; I < T; I += 4) acc += pcol[((int64_t)cstart + (I - B)) * 64 + r];
+  for (int I0 = B + 1 + part; I0 < T; I0 += 32) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int I = I0 + 4 * u;
+      v[u] = I < T ? pcol[((int64_t)cstart + (I - B)) * 64 + r] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += v[u];
+  }
   const double hd = reduce4(acc, sh);
   double sq = 0.0;
   if (tid < 64) {

@@ -1491,31 +1491,38 @@ __global__ __launch_bounds__(kThreads) void k_symv_tiles(
     I = j + (int)(t - start);
   }
   const int tid = threadIdx.x, r = tid & 63, part = tid >> 6;
+  const R* base = Hc + (int64_t)(64 * J) * ld + 64 * I;   // element (row r, col c) at c*ld + r
+  // every H load of the tile (both products) is issued before the first barrier
+  R hv[16], cv[16];
+#pragma unroll
+  for (int cc = 0; cc < 16; ++cc) {
+    // rows of block I: H[r][c] for the 16 columns of this part; on the diagonal tile the
+    // lower part only (the upper element mirrored)
+    const int cl = part * 16 + cc;
+    hv[cc] = (I != J || cl <= r) ? base[(int64_t)cl * ld + r] : base[(int64_t)r * ld + cl];
+  }
+  if (I != J) {
+    // rows of block J: column c of the tile, 16 contiguous rows
+    const R* col = base + (int64_t)r * ld + part * 16;
+#pragma unroll
+    for (int rr = 0; rr < 16; ++rr) cv[rr] = col[rr];
+  }
   if (tid < 64) {
     sd_col[tid] = d[64 * J + tid];
     sd_row[tid] = d[64 * I + tid];
   }
   __syncthreads();
-  const R* base = Hc + (int64_t)(64 * J) * ld + 64 * I;   // element (row r, col c) at c*ld + r
-  // rows of block I: sum_c H[r][c] d_J[c]; for the diagonal tile use the lower part only
+  // rows of block I: sum_c H[r][c] d_J[c]
   double a = 0.0;
-#pragma unroll 4
-  for (int cc = 0; cc < 16; ++cc) {
-    const int cl = part * 16 + cc;
-    R h;
-    if (I != J || cl <= r) h = base[(int64_t)cl * ld + r];
-    else h = base[(int64_t)r * ld + cl];
-    a = fma((double)h, sd_col[cl], a);
-  }
+#pragma unroll
+  for (int cc = 0; cc < 16; ++cc) a = fma((double)hv[cc], sd_col[part * 16 + cc], a);
   const double rowsum = reduce4(a, sh);
   if (tid < 64) prow[((int64_t)blockIdx.x) * 64 + tid] = rowsum;
   if (I != J) {
-    // rows of block J: sum_r H[r][c] d_I[r] (column c of the tile is contiguous)
-    const int cl = tid & 63;
+    // rows of block J: sum_r H[r][c] d_I[r], c = tid & 63
     double b2 = 0.0;
-    const R* col = base + (int64_t)cl * ld + part * 16;
-#pragma unroll 4
-    for (int rr = 0; rr < 16; ++rr) b2 = fma((double)col[rr], sd_row[part * 16 + rr], b2);
+#pragma unroll
+    for (int rr = 0; rr < 16; ++rr) b2 = fma((double)cv[rr], sd_row[part * 16 + rr], b2);
     const double colsum = reduce4(b2, sh);
     if (tid < 64) pcol[((int64_t)blockIdx.x) * 64 + tid] = colsum;
   }

@@ -41,9 +41,12 @@ __device__ double wg_max(double v, double* sh) {
   return r;
 }
 
-// Fixed-order sum of parts[0..n): thread i takes i, i+256, ...; then a fixed tree.
+// Fixed-order sum of parts[0..n): thread i takes i, i+256, ...; then a fixed tree.  The
+// per-thread loops here are unrolled so that a thread's loads are in flight together; the
+// order of each thread's additions is unchanged.
 __device__ double fixed_sum(const double* parts, int n, double* sh) {
   double v = 0.0;
+#pragma unroll 8
   for (int i = threadIdx.x; i < n; i += kThreads) v += parts[i];
   return wg_sum(v, sh);
 }
@@ -68,6 +71,7 @@ __global__ __launch_bounds__(kThreads) void k_lm_pre(LMState* st, const double* 
   if (need) {
     const double f = fixed_sum(cost_part, nblk, sh);
     double mx = 0.0, gg = 0.0;
+#pragma unroll 8
     for (int i = threadIdx.x; i < n8; i += kThreads) {
       mx = fmax(mx, diag[i]);
       gg = fma(g[i], g[i], gg);
@@ -107,6 +111,7 @@ __global__ __launch_bounds__(kThreads) void k_lm_post(LMState* st, const double*
     fnew = fixed_sum(cost_part, nblk, sh);
     const double mu = st->mu_eff;
     double v = 0.0;
+#pragma unroll 8
     for (int i = threadIdx.x; i < n8; i += kThreads) v = fma(d[i], fma(mu, d[i], g[i]), v);
     den = wg_sum(v, sh);
   }
@@ -137,6 +142,7 @@ __global__ __launch_bounds__(kThreads) void k_lm_post(LMState* st, const double*
   }
   __syncthreads();
   if (s_acc) {
+#pragma unroll 8
     for (int i = threadIdx.x; i < n8; i += kThreads) jones[i] += d[i];
   }
 }
@@ -146,6 +152,7 @@ __global__ __launch_bounds__(kThreads) void k_solve_setup(LMState* st, const dou
                                                           double mu, int refine_max) {
   __shared__ double sh[kThreads];
   double gg = 0.0;
+#pragma unroll 8
   for (int i = threadIdx.x; i < n; i += kThreads) gg = fma(g[i], g[i], gg);
   gg = wg_sum(gg, sh);
   if (threadIdx.x == 0) {

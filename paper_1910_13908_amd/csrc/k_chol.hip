@@ -1623,9 +1623,22 @@ __global__ __launch_bounds__(kThreads) void k_transpose_tiles(const R* __restric
   const int64_t k = first ? blockIdx.x : blockIdx.x - n1;
   const R* s = (first ? src : src2) + k * 4096;
   R* d = (first ? dst : dst2) + k * 4096;
-  for (int e = threadIdx.x; e < 4096; e += kThreads) t[e >> 6][e & 63] = s[e];
+  // all 16 loads of a thread are issued before the first LDS write (a loop that waited for
+  // each load in turn ran the kernel at half the rate)
+  R v[4096 / kThreads];
+#pragma unroll
+  for (int q = 0; q < 4096 / kThreads; ++q) v[q] = s[threadIdx.x + q * kThreads];
+#pragma unroll
+  for (int q = 0; q < 4096 / kThreads; ++q) {
+    const int e = threadIdx.x + q * kThreads;
+    t[e >> 6][e & 63] = v[q];
+  }
   __syncthreads();
-  for (int e = threadIdx.x; e < 4096; e += kThreads) d[e] = t[e & 63][e >> 6];
+#pragma unroll
+  for (int q = 0; q < 4096 / kThreads; ++q) {
+    const int e = threadIdx.x + q * kThreads;
+    d[e] = t[e & 63][e >> 6];
+  }
 }
 
 template <typename R>

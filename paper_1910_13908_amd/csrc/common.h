@@ -136,8 +136,9 @@ hipError_t launch_cost_adjoint(const ObsDev& o, int K, const R* res, const R* co
 
 // k_chol.hip
 // Factor H + mu I (mu from mu_dev if non-null); with g != null also y = L^{-1} g.
-// part: scratch of T * 2 * 4096 + T(T+1)/2 * 4096 + 64 T 64-bit slots: the worker's look-ahead
-// partial sums (FP64 raw; FP32 tagged with seq), the tagged copies of the handed-over tiles and
+// part: scratch of T * 2 * 4096 + T(T+1)/2 * 4096 + 64 T 64-bit slots: the worker's two
+// look-ahead tiles per step (FP64 raw; FP32 tagged with seq), the tagged copies of the
+// handed-over tiles and
 // the forward solve's block messages (FP32 only; kEmpty before the launch, and again after).
 // seq must differ from every earlier launch's on the same scratch and be nonzero, the tagged
 // part zeroed when the scratch is first used.  flags: T(T+1)/2 + 2T, zero between launches.

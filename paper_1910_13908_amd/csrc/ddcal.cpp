@@ -249,7 +249,7 @@ void layout_solve(Bump& bp, SolveBufs& b, int n, size_t es, int64_t B, int64_t n
   const size_t ntiles = (size_t)b.T * (b.T + 1) / 2;
   offs.push_back(bp.take(ntiles * 64 * sizeof(double)));               // prow
   offs.push_back(bp.take(ntiles * 64 * sizeof(double)));               // pcol
-  // Cholesky messages: partial sums (T x 2 tiles), tagged copies of the lower tiles, y blocks
+  // Cholesky messages: look-ahead tiles (T x 2), tagged copies of the lower tiles, y blocks
   offs.push_back(bp.take(((size_t)b.T * 2 * 4096 + (size_t)b.T * (b.T + 1) / 2 * 4096 +
                           (size_t)64 * b.T) * 8));
   offs.push_back(bp.take((size_t)b.T * (b.T + 1) / 2 * 4096 * es));    // LtT (transposed tiles)

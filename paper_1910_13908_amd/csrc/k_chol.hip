@@ -691,7 +691,7 @@ __device__ bool tagged_poll16(const uint64_t* p, uint32_t seq, Mfma<float>::acc_
 // In FP32 every tile a task hands to another (L_IJ, and in the slot of the diagonal tile
 // (s, s) the inverse X_s) is also written as a tagged copy in natural row-major order, slot e =
 // element e, and read from there, so no task publishes a flag or runs a fence.  The copies sit
-// after the partial-sum messages, tile t at t * 4096 (column-major tile order).
+// after the look-ahead tiles' messages, tile t at t * 4096 (column-major tile order).
 __device__ __forceinline__ uint64_t* tile_slots(void* base, int T, uint32_t ti) {
   return reinterpret_cast<uint64_t*>(base) + (int64_t)T * 2 * 16 * kThreads + (int64_t)ti * 4096;
 }

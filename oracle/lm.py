@@ -46,6 +46,9 @@ class LMInfo:
     nu: float = 2.0
     costs: List[float] = dataclasses.field(default_factory=list)   # f(x) after each iteration
     accepted: List[bool] = dataclasses.field(default_factory=list)
+    mu_effs: List[float] = dataclasses.field(default_factory=list)  # damping used in each iteration
+    mus: List[float] = dataclasses.field(default_factory=list)      # mu after each iteration
+    nus: List[float] = dataclasses.field(default_factory=list)      # nu after each iteration
 
 
 def damped_solve(H, g, mu_eff):
@@ -99,6 +102,9 @@ def lm_solve(Y, C, J0, ant_p, ant_q, n_iter, tau=1e-3, mu_floor=1e-6,
             nu = 2.0 * nu
         info.costs.append(f)
         info.accepted.append(accepted)
+        info.mu_effs.append(mu_eff)
+        info.mus.append(mu)
+        info.nus.append(nu)
     info.cost = f
     info.mu, info.nu = mu, nu
     return unpack_jones(x), info

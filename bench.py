@@ -85,7 +85,8 @@ def serve_measure(n_requests=200, n_slots=4, seed=0, precision="mixed"):
         reqs.append(dict(cfg=cfg, obs=obs, sky=sky, V=V, J0=J0, J=J0.clone(), K=ob.K, N=ob.N))
     torch.cuda.synchronize()
     ctx.close()
-    foot = max(dd.calibrate_footprint(r["obs"], r["K"], r["cfg"].n_sweeps, prec) for r in reqs)
+    foot = max(dd.calibrate_footprint(r["obs"], r["K"], r["cfg"].n_sweeps, r["cfg"].n_lm, prec)
+               for r in reqs)
     budget = int(n_slots * foot * 1.05) + (64 << 20)
     srv = dd.Server(0, n_slots=n_slots, hbm_budget_bytes=budget)
 

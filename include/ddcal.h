@@ -49,7 +49,7 @@ typedef enum {
   DDC_ENOMEM = -2,      /* workspace allocation failed */
   DDC_EDEVICE = -3,     /* HIP runtime error (message in ddc_last_error) */
   DDC_ENOTPD = -4,      /* damped normal matrix not positive definite (ddc_damped_solve) */
-  DDC_ENONFINITE = -5,  /* NaN/Inf in the inputs or the result */
+  DDC_ENONFINITE = -5,  /* NaN/Inf in the inputs, seen as a non-finite cost */
   DDC_ETIMEOUT = -6     /* an internal inter-workgroup wait exceeded its bound */
 } ddc_status;
 
@@ -101,6 +101,16 @@ typedef struct {
   double nu;
   int32_t fresh;
 } ddc_lm_state;
+
+/* Record of one LM iteration (host), in iteration order; a rejected step is recorded too. */
+typedef struct {
+  double cost;           /* f at the Jones held after the iteration (the trial's f if accepted) */
+  double mu_eff;         /* damping the step was solved with: max(mu, mu_floor * max diag) */
+  double mu;             /* mu after the iteration's update */
+  double nu;             /* nu after the iteration's update */
+  int32_t accepted;      /* 1 if the step was taken */
+  int32_t refine_steps;  /* FP64 refinement steps of the iteration (DDC_MIXED) */
+} ddc_lm_step;
 
 /* Per-solve report (host). */
 typedef struct {
@@ -154,56 +164,82 @@ ddc_status ddc_predict_factored(ddc_ctx* ctx, const ddc_obs* obs, const double* 
                                 const double* sv, const double* sw, const ddc_sky* sky,
                                 int32_t precision, void* coh);
 
-/* res = vis - sum_{k<K} J_k C_k J_k^H and (optionally) cost = ||res||^2 accumulated in FP64.
+/* Residual of the measurement equation over all clusters (paper Section 2: the sky is the
+ * sum of its clusters, each seen through its own Jones matrices; Section 3: every one of the
+ * N(N-1)/2 baselines): res = vis - sum_{k<K} J_k C_k J_k^H and (optionally) the cost
+ * f = ||res||^2, accumulated in FP64 in a fixed order.
  * vis, res: 8 planes [T][F][B]; coh: [K][8][T][F][B]; jones: [K][N][8].
- * res may be NULL (cost only); cost (HOST) may be NULL (no sync); res may alias vis. */
+ * res may be NULL (cost only); cost (HOST) may be NULL (no sync); res may alias vis.
+ * DDC_ENONFINITE if the cost is requested and is NaN/Inf (res is still written). */
 ddc_status ddc_residual(ddc_ctx* ctx, const ddc_obs* obs, int32_t n_clusters, const void* vis,
                         const void* coh, const double* jones, int32_t precision,
                         void* res, double* cost);
 
-/* out = in + alpha * sum_{k<K} J_k C_k J_k^H (alpha = +1 or -1); out may alias in.
- * Used to form synthetic data (in = noise) and the per-cluster data of a SAGE sweep. */
+/* out = in + alpha * sum_{k<K} J_k C_k J_k^H (alpha = +1 or -1); out may alias in: the
+ * model of clusters 0..K-1 (paper Section 2, one Jones solution per cluster) added to or
+ * taken from visibility planes.  Used to form synthetic data (in = noise) and the
+ * per-cluster data of a SAGE sweep. */
 ddc_status ddc_add_model(ddc_ctx* ctx, const ddc_obs* obs, int32_t n_clusters, const void* in,
                          const void* coh, const double* jones, double alpha,
                          int32_t precision, void* out);
 
-/* Normal equations of one cluster at jones_k ([N][8]): with y the cluster's data and coh_k
- * its coherencies ([8][T][F][B]), r = y - J_p C J_q^H and A = d(J_p C J_q^H)/dx,
- * JtJ = A^T A ([8N][8N] row-major, both triangles written) and Jtr = A^T r ([8N]), in
- * the precision's element type; cost (HOST, nullable) = ||r||^2 in FP64. */
+/* Gauss-Newton normal equations of one cluster (the per-cluster solve of paper Section 2;
+ * each of the N(N-1)/2 baselines of Section 3 couples its two stations' Jones) at jones_k
+ * ([N][8]): with y the cluster's data and coh_k its coherencies ([8][T][F][B]),
+ * r = y - J_p C J_q^H and A = d(J_p C J_q^H)/dx, JtJ = A^T A ([8N][8N] row-major, both
+ * triangles written; nullable) and Jtr = A^T r ([8N]; nullable), in the precision's element
+ * type; cost (HOST, nullable) = ||r||^2 in FP64 (synchronises).  DDC_ENONFINITE if the cost
+ * is requested and is NaN/Inf. */
 ddc_status ddc_build_normal_eq(ddc_ctx* ctx, const ddc_obs* obs, const void* y,
                                const void* coh_k, const double* jones_k, int32_t precision,
                                void* JtJ, void* Jtr, double* cost);
 
-/* Solve (H + mu I) d = g for symmetric H ([n][n] row-major; only the lower triangle is
- * read) with the library's blocked Cholesky; DDC_MIXED factors in FP32 and refines d in
- * FP64 (refine_tol / refine_max as in ddc_lm_opts).  H, g: element type of the precision;
- * d: double [n].  refine_steps (HOST, nullable) receives the steps taken.
- * DDC_ENOTPD if a pivot is not positive. */
+/* The damped linear solve of one LM step (Madsen, Nielsen & Tingleff 2004, Algorithm 3.16;
+ * the 8N x 8N system of the paper's per-cluster solve, N stations of Section 2):
+ * (H + mu I) d = g for symmetric H ([n][n] row-major; only the lower triangle is read) with
+ * the library's blocked Cholesky; DDC_MIXED factors in FP32 and refines d in FP64
+ * (refine_tol / refine_max as in ddc_lm_opts).  H, g: element type of the precision;
+ * d: double [n].  refine_steps (HOST, nullable) receives the steps taken.  Synchronises.
+ * DDC_ENOTPD if a pivot is not positive (d is then undefined); DDC_ETIMEOUT as for
+ * ddc_lm_solve. */
 ddc_status ddc_damped_solve(ddc_ctx* ctx, int32_t n, const void* H, const void* g, double mu,
                             int32_t precision, double refine_tol, int32_t refine_max,
                             double* d, int32_t* refine_steps);
 
-/* Levenberg-Marquardt on one cluster: y ([8][T][F][B]) is that cluster's data, coh_k its
- * coherencies; jones_k ([N][8], double) is the start and receives the result.
- * state (HOST, nullable = fresh start) is read and updated, so that calling again with it
- * continues the iteration exactly; info (HOST, nullable) receives the report.  The whole
- * iteration runs on the device (no host round trip per step); the call returns once the
- * result is on the device (it synchronises only if state or info is given). */
+/* Levenberg-Marquardt on one cluster (the per-cluster solve of the paper's Section 2: one
+ * calibration solution per cluster, over all N(N-1)/2 baselines of Section 3), with the
+ * damping schedule of Madsen, Nielsen & Tingleff (2004), Algorithm 3.16.
+ * y ([8][T][F][B]) is that cluster's data, coh_k its coherencies; jones_k ([N][8], double)
+ * is the start and receives the result.  state (HOST, nullable = fresh start) is read and
+ * updated, so that calling again with it continues the iteration exactly; info (HOST,
+ * nullable) receives the report; trace (HOST, nullable, [opts->n_iter]) receives one
+ * ddc_lm_step per iteration.  The whole iteration runs on the device (no host round trip per
+ * step); the call synchronises the stream once at the end to read the solve's status.
+ * Errors: DDC_ENONFINITE if the cost at a built point is NaN/Inf (NaN/Inf in y, coh_k or
+ * jones_k; the Jones are then left as they were), DDC_ETIMEOUT if an inter-workgroup wait
+ * of the factorisation or the solves exceeded its bound (every later step of the call is
+ * rejected, so the Jones hold the last accepted point).  A factorisation that finds a
+ * non-positive pivot is not an error: the step is rejected (counted in n_notpd). */
 ddc_status ddc_lm_solve(ddc_ctx* ctx, const ddc_obs* obs, const void* y, const void* coh_k,
                         double* jones_k, const ddc_lm_opts* opts, ddc_lm_state* state,
-                        ddc_lm_info* info);
+                        ddc_lm_info* info, ddc_lm_step* trace);
 
-/* Full calibration: predict all clusters, then n_sweeps SAGE sweeps; in each sweep every
- * cluster k in index order gets Y_k = R + J_k C_k J_k^H, n_iter LM iterations on Y_k (mu
- * restarted from tau), and R = Y_k - J_k C_k J_k^H.  vis: data; jones: [K][N][8] start and
- * result; res (nullable) receives the final residual R; info (HOST, nullable) receives
- * [n_sweeps][K] reports (synchronises). */
+/* Full calibration (paper Section 2: a sky grouped into clusters, one solution per cluster,
+ * solved for one cluster at a time): predict all clusters, then n_sweeps SAGE sweeps; in
+ * each sweep every cluster k in index order gets Y_k = R + J_k C_k J_k^H, n_iter LM
+ * iterations on Y_k (ddc_lm_solve's method, mu restarted from tau), and
+ * R = Y_k - J_k C_k J_k^H.  vis: data; jones: [K][N][8] start and result; res (nullable)
+ * receives the final residual R; info (HOST, nullable) receives [n_sweeps][K] reports;
+ * trace (HOST, nullable) receives [n_sweeps][K][n_iter] iteration records.  The call
+ * synchronises the stream once at the end to read the solves' status; errors as for
+ * ddc_lm_solve (DDC_ENONFINITE, DDC_ETIMEOUT), reported for the whole calibration. */
 ddc_status ddc_calibrate(ddc_ctx* ctx, const ddc_obs* obs, const ddc_sky* sky, const void* vis,
                          double* jones, const ddc_cal_opts* opts, void* res,
-                         ddc_lm_info* info);
+                         ddc_lm_info* info, ddc_lm_step* trace);
 
-/* Gradient of f = ||vis - sum_{k<K} J_k C_k J_k^H||^2 with respect to every cluster's Jones
+/* Gradient of the calibration cost (the per-cluster solves of paper Section 2 minimise it
+ * cluster by cluster; this is its derivative for all clusters at once)
+ * f = ||vis - sum_{k<K} J_k C_k J_k^H||^2 with respect to every cluster's Jones
  * in the real-pair layout of `jones`: grad[k][p][2e+c] = df/d(Re or Im of (J_{p,k})_e)
  * (double, [K][N][8]).  A hand-written adjoint kernel: df/dx_k = -2 (sum R G^H + sum R^H Hm)
  * per station with G = C J_q^H, Hm = J_p C.  cost (HOST, nullable) receives f and makes the
@@ -225,6 +261,7 @@ typedef struct ddc_server ddc_server;
 
 /* Bytes of workspace ddc_calibrate (and the server) needs for this problem; -1 if invalid. */
 int64_t ddc_calibrate_footprint(const ddc_obs* obs, int32_t n_clusters, int32_t n_sweeps,
+                                int32_t n_iter,
                                 int32_t precision);
 /* Server on `device` with n_slots concurrent solves (1..64) and an HBM arena of
  * hbm_budget_bytes (>= 64 KiB) allocated up front (DDC_ENOMEM if that fails). */

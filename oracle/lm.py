@@ -49,6 +49,7 @@ class LMInfo:
     mu_effs: List[float] = dataclasses.field(default_factory=list)  # damping used in each iteration
     mus: List[float] = dataclasses.field(default_factory=list)      # mu after each iteration
     nus: List[float] = dataclasses.field(default_factory=list)      # nu after each iteration
+    trial_costs: List[float] = dataclasses.field(default_factory=list)  # f(x + d) (nan: no step)
 
 
 def damped_solve(H, g, mu_eff):
@@ -80,6 +81,7 @@ def lm_solve(Y, C, J0, ant_p, ant_q, n_iter, tau=1e-3, mu_floor=1e-6,
         mu_eff = max(mu, mu_floor * float(np.max(np.diag(H))))
         d = damped_solve(H, g, mu_eff)
         accepted = False
+        f_new = float("nan")
         if d is None:
             info.n_notpd += 1
         else:
@@ -105,6 +107,7 @@ def lm_solve(Y, C, J0, ant_p, ant_q, n_iter, tau=1e-3, mu_floor=1e-6,
         info.mu_effs.append(mu_eff)
         info.mus.append(mu)
         info.nus.append(nu)
+        info.trial_costs.append(f_new)
     info.cost = f
     info.mu, info.nu = mu, nu
     return unpack_jones(x), info

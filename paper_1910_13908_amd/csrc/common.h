@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "ddcal.h"
+
 namespace ddc {
 
 constexpr double kCLight = 299792458.0;
@@ -33,7 +35,7 @@ struct LMState {
   int32_t n_accept, n_reject, n_notpd;
   int32_t timeout;        // an inter-workgroup wait exceeded its bound
   int32_t iter;           // iterations done
-  int32_t pad;
+  int32_t nonfinite;      // the cost at a built point was NaN/Inf
 };
 
 // Scratch for the persistent kernels: ticket counters, exit counter and per-tile flags.
@@ -179,8 +181,10 @@ hipError_t launch_lm_init(LMState* st, int fresh, double mu, double nu, hipStrea
 hipError_t launch_lm_pre(LMState* st, const double* cost_part, int nblk, const double* diag,
                          int n8, const double* g, double tau, double mu_floor, int refine_max,
                          hipStream_t s);
+// trace (nullable): the iteration's record goes to trace[iter].
 hipError_t launch_lm_post(LMState* st, const double* cost_part, int nblk, const double* d,
-                          const double* g, int n8, double* jones, hipStream_t s);
+                          const double* g, int n8, double* jones, ddc_lm_step* trace,
+                          hipStream_t s);
 hipError_t launch_solve_setup(LMState* st, const double* g, int n, double mu, int refine_max,
                               hipStream_t s);
 hipError_t launch_copy_state(const LMState* st, LMState* dst, hipStream_t s);

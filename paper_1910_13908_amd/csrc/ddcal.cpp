@@ -342,7 +342,8 @@ ddc_status enqueue_solve(ddc_ctx* c, SolveBufs& b, LMState* lm, int refine_max, 
 // n_iter LM iterations for one cluster; Jones updated in place on the device.
 template <typename R>
 ddc_status enqueue_lm(ddc_ctx* c, const ObsDev& o, const R* y, const R* coh, double* jones,
-                      const ddc_lm_opts& opt, SolveBufs& b, int fresh, double mu, double nu) {
+                      const ddc_lm_opts& opt, SolveBufs& b, int fresh, double mu, double nu,
+                      ddc_lm_step* trace) {
   hipStream_t st = c->stream;
   LMState* lm = c->lm();
   const int refine_max = opt.precision == DDC_MIXED ? opt.refine_max : 0;
@@ -366,7 +367,7 @@ ddc_status enqueue_lm(ddc_ctx* c, const ObsDev& o, const R* y, const R* coh, dou
     DDCCK(timed(c, T_TRIAL, vis * 16 * es, [&] {
       return launch_trial_cost<R>(o, y, coh, jones, b.d, b.cost_part, &nblk, lm, st);
     }));
-    HIPCK(launch_lm_post(lm, b.cost_part, nblk, b.d, b.g, n8, jones, st));
+    HIPCK(launch_lm_post(lm, b.cost_part, nblk, b.d, b.g, n8, jones, trace, st));
   }
   return DDC_OK;
 }
@@ -378,6 +379,14 @@ ddc_status check_lm_opts(ddc_ctx* c, const ddc_lm_opts* opt) {
   if (!(opt->tau > 0.0) || !(opt->mu_floor >= 0.0) || !(opt->refine_tol >= 0.0))
     return fail(c, DDC_EINVAL, "tau must be > 0, mu_floor and refine_tol >= 0");
   if (opt->refine_max < 0 || opt->refine_max > 8) return fail(c, DDC_EINVAL, "refine_max must be in 0..8");
+  return DDC_OK;
+}
+
+// Status of a finished solve from its device state: a timed-out wait first (its results are
+// incomplete), then a non-finite cost.
+ddc_status solve_status(ddc_ctx* c, const LMState& h) {
+  if (h.timeout || (h.notpd & 2)) return fail(c, DDC_ETIMEOUT, "an inter-workgroup wait timed out");
+  if (h.nonfinite) return fail(c, DDC_ENONFINITE, "the cost is not finite (NaN/Inf in the data, coherencies or Jones)");
   return DDC_OK;
 }
 
@@ -569,6 +578,7 @@ ddc_status add_model_impl(ddc_ctx* c, const ObsDev& o, int K, const void* in, co
     HIPCK(launch_sum(parts, nb, total, c->stream));
     HIPCK(hipMemcpyAsync(cost, total, sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCK(hipStreamSynchronize(c->stream));
+    if (!std::isfinite(*cost)) return fail(c, DDC_ENONFINITE, "the cost is not finite");
   }
   return DDC_OK;
 }
@@ -634,6 +644,7 @@ ddc_status build_neq_impl(ddc_ctx* c, const ObsDev& o, const void* y, const void
     HIPCK(launch_sum(b.cost_part, nblk, b.scalar, st));
     HIPCK(hipMemcpyAsync(cost, b.scalar, sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCK(hipStreamSynchronize(st));
+    if (!std::isfinite(*cost)) return fail(c, DDC_ENONFINITE, "the cost is not finite");
   }
   return DDC_OK;
 }
@@ -709,30 +720,35 @@ namespace {
 template <typename R>
 ddc_status lm_solve_impl(ddc_ctx* c, const ObsDev& o, const void* y, const void* coh_k,
                          double* jones, const ddc_lm_opts& opt, ddc_lm_state* state,
-                         ddc_lm_info* info) {
+                         ddc_lm_info* info, ddc_lm_step* trace) {
   Bump bp;
   SolveBufs b;
   std::vector<size_t> offs;
   layout_solve(bp, b, 8 * o.N, sizeof(R), o.B, (o.B + 255) / 256, offs);
+  const size_t o_trace = bp.take((size_t)(opt.n_iter > 0 ? opt.n_iter : 1) * sizeof(ddc_lm_step));
   DDCCK(ensure_ws(c, bp.off));
   bind_solve(c, b, offs);
   DDCCK(prepare_matrix<R>(c, b));
+  ddc_lm_step* dtrace = reinterpret_cast<ddc_lm_step*>(c->ws + o_trace);
   const int fresh = (!state || state->fresh) ? 1 : 0;
   DDCCK(enqueue_lm<R>(c, o, reinterpret_cast<const R*>(y), reinterpret_cast<const R*>(coh_k), jones,
-                      opt, b, fresh, fresh ? 0.0 : state->mu, fresh ? 2.0 : state->nu));
-  if (state || info) {
-    LMState h;
-    HIPCK(hipMemcpyAsync(&h, c->lm(), sizeof h, hipMemcpyDeviceToHost, c->stream));
-    HIPCK(hipStreamSynchronize(c->stream));
-    if (h.timeout || (h.notpd & 2)) return fail(c, DDC_ETIMEOUT, "an inter-workgroup wait timed out");
-    if (state) {
-      state->mu = h.mu;
-      state->nu = h.nu;
-      state->fresh = 0;
-    }
-    if (info) fill_info(h, info);
+                      opt, b, fresh, fresh ? 0.0 : state->mu, fresh ? 2.0 : state->nu,
+                      trace ? dtrace : nullptr));
+  // the solve's status is always read back (one small copy), so a timed-out wait or a
+  // non-finite cost is reported even when the caller asks for no report
+  LMState h;
+  HIPCK(hipMemcpyAsync(&h, c->lm(), sizeof h, hipMemcpyDeviceToHost, c->stream));
+  if (trace && opt.n_iter > 0)
+    HIPCK(hipMemcpyAsync(trace, dtrace, (size_t)opt.n_iter * sizeof(ddc_lm_step),
+                         hipMemcpyDeviceToHost, c->stream));
+  HIPCK(hipStreamSynchronize(c->stream));
+  if (state) {
+    state->mu = h.mu;
+    state->nu = h.nu;
+    state->fresh = 0;
   }
-  return DDC_OK;
+  if (info) fill_info(h, info);
+  return solve_status(c, h);
 }
 }  // namespace
 
@@ -740,7 +756,7 @@ extern "C" {
 
 ddc_status ddc_lm_solve(ddc_ctx* c, const ddc_obs* obs, const void* y, const void* coh_k,
                         double* jones_k, const ddc_lm_opts* opts, ddc_lm_state* state,
-                        ddc_lm_info* info) {
+                        ddc_lm_info* info, ddc_lm_step* trace) {
   if (!c) return DDC_EINVAL;
   (void)hipSetDevice(c->device);
   ObsDev o;
@@ -749,8 +765,9 @@ ddc_status ddc_lm_solve(ddc_ctx* c, const ddc_obs* obs, const void* y, const voi
   if (!y || !coh_k || !jones_k) return fail(c, DDC_EINVAL, "y, coh_k and jones_k must not be NULL");
   if (state && !state->fresh && !(state->mu > 0.0 && state->nu >= 2.0))
     return fail(c, DDC_EINVAL, "resumed state needs mu > 0 and nu >= 2");
-  if (opts->precision == DDC_MIXED) return lm_solve_impl<float>(c, o, y, coh_k, jones_k, *opts, state, info);
-  return lm_solve_impl<double>(c, o, y, coh_k, jones_k, *opts, state, info);
+  if (opts->precision == DDC_MIXED)
+    return lm_solve_impl<float>(c, o, y, coh_k, jones_k, *opts, state, info, trace);
+  return lm_solve_impl<double>(c, o, y, coh_k, jones_k, *opts, state, info, trace);
 }
 
 }  // extern "C"
@@ -760,10 +777,11 @@ namespace {
 // Workspace layout of one calibration (shared by ddc_calibrate and the server's footprint).
 struct CalLayout {
   std::vector<size_t> solve_offs;
-  size_t o_coh, o_R, o_Y, o_off, o_info, total;
+  size_t o_coh, o_R, o_Y, o_off, o_info, o_trace, total;
 };
 
-CalLayout layout_calibrate(const ObsDev& o, int K, int n_sweeps, size_t es, SolveBufs& b) {
+CalLayout layout_calibrate(const ObsDev& o, int K, int n_sweeps, int n_iter, size_t es,
+                           SolveBufs& b) {
   CalLayout L;
   const int64_t plane = (int64_t)o.T * o.F * o.B;
   Bump bp;
@@ -774,6 +792,8 @@ CalLayout layout_calibrate(const ObsDev& o, int K, int n_sweeps, size_t es, Solv
   L.o_off = bp.take((size_t)(K + 1) * sizeof(int32_t));
   const int n_info = n_sweeps * K;
   L.o_info = bp.take((size_t)(n_info > 0 ? n_info : 1) * sizeof(LMState));
+  const int64_t n_trace = (int64_t)n_info * (n_iter > 0 ? n_iter : 0);
+  L.o_trace = bp.take((size_t)(n_trace > 0 ? n_trace : 1) * sizeof(ddc_lm_step));
   L.total = bp.off;
   return L;
 }
@@ -783,16 +803,16 @@ CalLayout layout_calibrate(const ObsDev& o, int K, int n_sweeps, size_t es, Solv
 namespace ddc {
 namespace host {
 
-int64_t calibrate_footprint(const ObsDev& o, int K, int n_sweeps, int prec) {
+int64_t calibrate_footprint(const ObsDev& o, int K, int n_sweeps, int n_iter, int prec) {
   SolveBufs b;
-  return (int64_t)layout_calibrate(o, K, n_sweeps, esize(prec), b).total;
+  return (int64_t)layout_calibrate(o, K, n_sweeps, n_iter, esize(prec), b).total;
 }
 
 ddc_status prepare_calibrate(ddc_ctx* c, const ObsDev& o, const ddc_sky* sky, int n_sweeps,
-                             int prec, CalBufs& cb) {
+                             int n_iter, int prec, CalBufs& cb) {
   const int K = sky->n_clusters;
   SolveBufs b;
-  const CalLayout L = layout_calibrate(o, K, n_sweeps, esize(prec), b);
+  const CalLayout L = layout_calibrate(o, K, n_sweeps, n_iter, esize(prec), b);
   DDCCK(ensure_ws(c, L.total));
   bind_solve(c, b, L.solve_offs);
   if (prec == DDC_MIXED) DDCCK(prepare_matrix<float>(c, b));
@@ -803,7 +823,9 @@ ddc_status prepare_calibrate(ddc_ctx* c, const ObsDev& o, const ddc_sky* sky, in
   cb.Yb = c->ws + L.o_Y;
   cb.doffs = reinterpret_cast<int32_t*>(c->ws + L.o_off);
   cb.dinfo = reinterpret_cast<LMState*>(c->ws + L.o_info);
+  cb.dtrace = reinterpret_cast<ddc_lm_step*>(c->ws + L.o_trace);
   cb.n_info = n_sweeps * K;
+  cb.n_iter = n_iter;
   cb.K = K;
   cb.prec = prec;
   cb.offs_host.assign(sky->cluster_offset, sky->cluster_offset + K + 1);
@@ -839,7 +861,8 @@ ddc_status enqueue_sage_t(ddc_ctx* c, const ObsDev& o, const void* vis, double* 
       DDCCK(timed(c, T_MODEL, (double)plane * 24.0 * es, [&] {
         return launch_add_model<R>(o, k, k + 1, Rb, coh, jones, 1.0, Yb, nullptr, nullptr, st);
       }));
-      DDCCK(enqueue_lm<R>(c, o, Yb, ck, jk, opt.lm, b, 1, 0.0, 2.0));
+      DDCCK(enqueue_lm<R>(c, o, Yb, ck, jk, opt.lm, b, 1, 0.0, 2.0,
+                          cb.dtrace + (int64_t)(e * K + k) * opt.lm.n_iter));
       DDCCK(timed(c, T_MODEL, (double)plane * 24.0 * es, [&] {
         return launch_add_model<R>(o, k, k + 1, Yb, coh, jones, -1.0, Rb, nullptr, nullptr, st);
       }));
@@ -855,17 +878,26 @@ ddc_status enqueue_sage(ddc_ctx* c, const ObsDev& o, const void* vis, double* jo
   return enqueue_sage_t<double>(c, o, vis, jones, opt, cb);
 }
 
-ddc_status collect_infos(ddc_ctx* c, CalBufs& cb, ddc_lm_info* info) {
-  if (!info || cb.n_info <= 0) return DDC_OK;
+ddc_status collect_infos(ddc_ctx* c, CalBufs& cb, ddc_lm_info* info, ddc_lm_step* trace) {
+  if (cb.n_info <= 0) return DDC_OK;
+  // every visit's state is read back whether or not reports are wanted: it carries the
+  // timeout and non-finite flags that decide the call's status
   std::vector<LMState> h(cb.n_info);
   HIPCK(hipMemcpyAsync(h.data(), cb.dinfo, cb.n_info * sizeof(LMState), hipMemcpyDeviceToHost, c->stream));
+  const size_t n_trace = (size_t)cb.n_info * (cb.n_iter > 0 ? cb.n_iter : 0);
+  if (trace && n_trace > 0)
+    HIPCK(hipMemcpyAsync(trace, cb.dtrace, n_trace * sizeof(ddc_lm_step), hipMemcpyDeviceToHost,
+                         c->stream));
   HIPCK(hipStreamSynchronize(c->stream));
-  bool to = false;
+  ddc_status st = DDC_OK;
   for (int i = 0; i < cb.n_info; ++i) {
-    fill_info(h[i], info + i);
-    to = to || h[i].timeout || (h[i].notpd & 2);
+    if (info) fill_info(h[i], info + i);
+    const ddc_status si = solve_status(c, h[i]);
+    if (si == DDC_ETIMEOUT || (si != DDC_OK && st == DDC_OK)) st = si;
   }
-  if (to) return fail(c, DDC_ETIMEOUT, "an inter-workgroup wait timed out");
+  if (st == DDC_ETIMEOUT) return fail(c, st, "an inter-workgroup wait timed out");
+  if (st != DDC_OK)
+    return fail(c, st, "the cost is not finite (NaN/Inf in the data, coherencies or Jones)");
   return DDC_OK;
 }
 
@@ -885,12 +917,13 @@ const char* ctx_error(ddc_ctx* c) { return c->err.c_str(); }
 namespace {
 template <typename R>
 ddc_status calibrate_impl(ddc_ctx* c, const ObsDev& o, const ddc_sky* sky, const void* vis,
-                          double* jones, const ddc_cal_opts& opt, void* res, ddc_lm_info* info) {
+                          double* jones, const ddc_cal_opts& opt, void* res, ddc_lm_info* info,
+                          ddc_lm_step* trace) {
   using namespace ddc::host;
   const int K = sky->n_clusters;
   const int64_t plane = (int64_t)o.T * o.F * o.B;
   CalBufs cb;
-  DDCCK(prepare_calibrate(c, o, sky, opt.n_sweeps, opt.lm.precision, cb));
+  DDCCK(prepare_calibrate(c, o, sky, opt.n_sweeps, opt.lm.n_iter, opt.lm.precision, cb));
   struct Guard { CalBufs& cb; ~Guard() { release_calibrate(cb); } } guard{cb};
   hipStream_t st = c->stream;
   const double terms = (double)sky->cluster_offset[K] * plane;
@@ -900,15 +933,15 @@ ddc_status calibrate_impl(ddc_ctx* c, const ObsDev& o, const ddc_sky* sky, const
   }));
   DDCCK(enqueue_sage(c, o, vis, jones, opt, cb));
   if (res) HIPCK(hipMemcpyAsync(res, cb.Rb, (size_t)8 * plane * sizeof(R), hipMemcpyDeviceToDevice, st));
-  if (info) DDCCK(collect_infos(c, cb, info));
-  return DDC_OK;
+  return collect_infos(c, cb, info, trace);
 }
 }  // namespace
 
 extern "C" {
 
 ddc_status ddc_calibrate(ddc_ctx* c, const ddc_obs* obs, const ddc_sky* sky, const void* vis,
-                         double* jones, const ddc_cal_opts* opts, void* res, ddc_lm_info* info) {
+                         double* jones, const ddc_cal_opts* opts, void* res, ddc_lm_info* info,
+                         ddc_lm_step* trace) {
   if (!c) return DDC_EINVAL;
   (void)hipSetDevice(c->device);
   ObsDev o;
@@ -925,8 +958,9 @@ ddc_status ddc_calibrate(ddc_ctx* c, const ddc_obs* obs, const ddc_sky* sky, con
       return fail(c, DDC_EINVAL, "cluster_offset must be non-decreasing");
   if (sky->cluster_offset[K] > 0 && (!sky->l || !sky->m || !sky->I || !sky->Q || !sky->U || !sky->V))
     return fail(c, DDC_EINVAL, "sky arrays must not be NULL");
-  if (opts->lm.precision == DDC_MIXED) return calibrate_impl<float>(c, o, sky, vis, jones, *opts, res, info);
-  return calibrate_impl<double>(c, o, sky, vis, jones, *opts, res, info);
+  if (opts->lm.precision == DDC_MIXED)
+    return calibrate_impl<float>(c, o, sky, vis, jones, *opts, res, info, trace);
+  return calibrate_impl<double>(c, o, sky, vis, jones, *opts, res, info, trace);
 }
 
 }  // extern "C"

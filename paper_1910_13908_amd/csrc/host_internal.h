@@ -18,17 +18,19 @@ struct CalBufs {
   void* Yb = nullptr;          // per-cluster data planes
   int32_t* doffs = nullptr;    // cluster offsets on the device
   LMState* dinfo = nullptr;    // per-visit LM reports [n_sweeps][K]
-  int n_info = 0, K = 0, prec = 0;
+  ddc_lm_step* dtrace = nullptr;  // per-iteration records [n_sweeps][K][n_iter]
+  int n_info = 0, n_iter = 0, K = 0, prec = 0;
   std::vector<int32_t> offs_host;
 };
 
-int64_t calibrate_footprint(const ObsDev& o, int K, int n_sweeps, int prec);
+int64_t calibrate_footprint(const ObsDev& o, int K, int n_sweeps, int n_iter, int prec);
 ddc_status prepare_calibrate(ddc_ctx* c, const ObsDev& o, const ddc_sky* sky, int n_sweeps,
-                             int prec, CalBufs& cb);
+                             int n_iter, int prec, CalBufs& cb);
 void release_calibrate(CalBufs& cb);
 ddc_status enqueue_sage(ddc_ctx* c, const ObsDev& o, const void* vis, double* jones,
                         const ddc_cal_opts& opt, CalBufs& cb);
-ddc_status collect_infos(ddc_ctx* c, CalBufs& cb, ddc_lm_info* info);
+// Reads every visit's state back; info and trace (HOST, nullable) receive the reports.
+ddc_status collect_infos(ddc_ctx* c, CalBufs& cb, ddc_lm_info* info, ddc_lm_step* trace);
 ddc_status ctx_obs(ddc_ctx* c, const ddc_obs* obs, ObsDev& o);
 hipStream_t ctx_stream(ddc_ctx* c);
 void ctx_lend_workspace(ddc_ctx* c, void* ws, size_t bytes);

@@ -1148,11 +1148,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
 // r = tid & 63 (row or column of the tile), part = tid >> 6 (a quarter of the other index).
 // ---------------------------------------------------------------------------------------
 
-// Gate: 0 = always run, 1 = skip if the factorisation failed, 2 = also skip once the
-// refinement has converged.
+// Gate: 0 = always run, 1 = skip if the factorisation failed or an earlier wait of the
+// solve timed out, 2 = also skip once the refinement has converged.
 __device__ __forceinline__ bool gated(const LMState* lm, int gate) {
   if (!lm || gate == 0) return false;
-  if (lm->notpd) return true;
+  if (lm->notpd || lm->timeout) return true;
   return gate == 2 && lm->refine_done;
 }
 

@@ -7,8 +7,10 @@
 //         mu_eff = max(mu, mu_floor * max diag H)  (floor against the gauge null space)
 //   post: f' = ||r(x + d)||^2, rho = (f - f') / (d . (mu_eff d + g));
 //         rho > 0: x += d, f = f', mu *= max(1/3, 1 - (2 rho - 1)^3), nu = 2, rebuild;
-//         else (also when the factorisation failed or the denominator is not positive):
-//         mu *= nu, nu *= 2.
+//         else (also when the factorisation failed, an inter-workgroup wait of the solve
+//         timed out, or the denominator is not positive): mu *= nu, nu *= 2.
+// A non-finite cost at a built point (NaN/Inf in the data, coherencies or Jones) is flagged
+// for the host; its steps are all rejected since no trial cost compares below it.
 // The denominator is the decrease predicted by the Gauss-Newton model of f = ||r||^2.
 #include "common.h"
 
@@ -80,6 +82,7 @@ __global__ __launch_bounds__(kThreads) void k_lm_pre(LMState* st, const double* 
     gg = wg_sum(gg, sh);
     if (threadIdx.x == 0) {
       st->f = f;
+      if (!isfinite(f)) st->nonfinite = 1;
       st->maxdiag = mx;
       st->g_norm2 = gg;
       if (st->iter == 0) st->f0 = f;
@@ -102,10 +105,12 @@ __global__ __launch_bounds__(kThreads) void k_lm_pre(LMState* st, const double* 
 __global__ __launch_bounds__(kThreads) void k_lm_post(LMState* st, const double* cost_part,
                                                       int nblk, const double* d,
                                                       const double* g, int n8,
-                                                      double* jones) {
+                                                      double* jones, ddc_lm_step* trace) {
   __shared__ double sh[kThreads];
   __shared__ int s_acc;
-  const int fail = st->notpd;
+  // bit 0: not positive definite; bit 1: a wait of the factorisation timed out; a timed-out
+  // wait of a triangular solve or refinement step leaves d unfinished, so it fails as well
+  const int fail = st->notpd | (st->timeout ? 2 : 0);
   double fnew = 0.0, den = 0.0;
   if (!fail) {
     fnew = fixed_sum(cost_part, nblk, sh);
@@ -123,6 +128,7 @@ __global__ __launch_bounds__(kThreads) void k_lm_post(LMState* st, const double*
       acc = rho > 0.0;
     }
     if (fail & 2) st->timeout = 1;
+    const double mu_eff = st->mu_eff;
     if (acc) {
       st->f = fnew;
       const double t = 2.0 * rho - 1.0;
@@ -134,9 +140,19 @@ __global__ __launch_bounds__(kThreads) void k_lm_post(LMState* st, const double*
       st->mu *= st->nu;
       st->nu *= 2.0;
       st->n_reject += 1;
-      if (fail) st->n_notpd += 1;
+      if (fail & 1) st->n_notpd += 1;
     }
     if (st->refine_steps > st->max_refine) st->max_refine = st->refine_steps;
+    if (trace) {
+      ddc_lm_step r;
+      r.cost = st->f;
+      r.mu_eff = mu_eff;
+      r.mu = st->mu;
+      r.nu = st->nu;
+      r.accepted = acc;
+      r.refine_steps = st->refine_steps;
+      trace[st->iter] = r;
+    }
     st->iter += 1;
     s_acc = acc;
   }
@@ -211,9 +227,10 @@ hipError_t launch_lm_pre(LMState* st, const double* cost_part, int nblk, const d
   return hipGetLastError();
 }
 hipError_t launch_lm_post(LMState* st, const double* cost_part, int nblk, const double* d,
-                          const double* g, int n8, double* jones, hipStream_t s) {
+                          const double* g, int n8, double* jones, ddc_lm_step* trace,
+                          hipStream_t s) {
   hipLaunchKernelGGL(k_lm_post, dim3(1), dim3(kThreads), 0, s, st, cost_part, nblk, d, g, n8,
-                     jones);
+                     jones, trace);
   return hipGetLastError();
 }
 hipError_t launch_solve_setup(LMState* st, const double* g, int n, double mu, int refine_max,

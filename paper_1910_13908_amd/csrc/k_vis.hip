@@ -355,7 +355,7 @@ __global__ __launch_bounds__(kThreads) void k_trial_cost(
     const double* __restrict__ d, const int32_t* __restrict__ ant_p,
     const int32_t* __restrict__ ant_q, int64_t B, int TF, double* __restrict__ cost_part,
     const LMState* __restrict__ lm) {
-  if (lm && lm->notpd) return;
+  if (lm && (lm->notpd || lm->timeout)) return;
   __shared__ double sh[kThreads / 64];
   const int64_t b = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const int64_t plane = (int64_t)TF * B;

@@ -178,7 +178,7 @@ void retire(ddc_server* s, bool& any) {
       st = DDC_EDEVICE;
       msg = hipGetErrorString(q);
     } else {
-      st = host::collect_infos(sl.ctx, r->cb, r->info.data());
+      st = host::collect_infos(sl.ctx, r->cb, r->info.data(), nullptr);
       if (st != DDC_OK) msg = host::ctx_error(sl.ctx);
     }
     host::release_calibrate(r->cb);
@@ -260,6 +260,7 @@ void admit(ddc_server* s, bool& any) {
     ddc_status st = ddc_set_stream(sl.ctx, sl.stream);
     if (st == DDC_OK) st = host::ctx_obs(sl.ctx, &r->obs, r->od);
     if (st == DDC_OK) st = host::prepare_calibrate(sl.ctx, r->od, &r->sky, r->opts.n_sweeps,
+                                                   r->opts.lm.n_iter,
                                                    r->opts.lm.precision, r->cb);
     if (st == DDC_OK && hipEventRecord(sl.ready, sl.stream) != hipSuccess) st = DDC_EDEVICE;
     if (st == DDC_OK && hipStreamWaitEvent(s->batch_stream, sl.ready, 0) != hipSuccess) st = DDC_EDEVICE;
@@ -298,6 +299,9 @@ void admit(ddc_server* s, bool& any) {
     if (st == DDC_OK) st = host::enqueue_sage(sl.ctx, r->od, r->vis, r->jones, r->opts, r->cb);
     if (st == DDC_OK && hipEventRecord(sl.done, sl.stream) != hipSuccess) st = DDC_EDEVICE;
     if (st != DDC_OK) {
+      // the request's predict may already be queued on the batch stream, writing into its
+      // arena range: both streams must be idle before the range can be handed out again
+      (void)hipStreamSynchronize(s->batch_stream);
       (void)hipStreamSynchronize(sl.stream);
       std::string msg = e != hipSuccess ? hipGetErrorString(e) : host::ctx_error(sl.ctx);
       host::release_calibrate(r->cb);
@@ -363,11 +367,11 @@ ObsDev size_only(const ddc_obs* obs) {
 extern "C" {
 
 int64_t ddc_calibrate_footprint(const ddc_obs* obs, int32_t n_clusters, int32_t n_sweeps,
-                                int32_t precision) {
+                                int32_t n_iter, int32_t precision) {
   if (!obs || obs->n_stations < 2 || obs->n_times < 1 || obs->n_chans < 1 || n_clusters < 1 ||
-      n_sweeps < 0 || (precision != DDC_FP64 && precision != DDC_MIXED))
+      n_sweeps < 0 || n_iter < 0 || (precision != DDC_FP64 && precision != DDC_MIXED))
     return -1;
-  return host::calibrate_footprint(size_only(obs), n_clusters, n_sweeps, precision);
+  return host::calibrate_footprint(size_only(obs), n_clusters, n_sweeps, n_iter, precision);
 }
 
 ddc_status ddc_server_create(ddc_server** out, int32_t device, int32_t n_slots,
@@ -444,7 +448,8 @@ ddc_status ddc_server_submit(ddc_server* s, const ddc_obs* obs, const ddc_sky* s
   if (!s || !id) return DDC_EINVAL;
   ddc_status st = check_request(s, obs, sky, vis, jones, opts);
   if (st != DDC_OK) return st;
-  const int64_t bytes = ddc_calibrate_footprint(obs, sky->n_clusters, opts->n_sweeps, opts->lm.precision);
+  const int64_t bytes = ddc_calibrate_footprint(obs, sky->n_clusters, opts->n_sweeps,
+                                                opts->lm.n_iter, opts->lm.precision);
   if (bytes < 0 || bytes > s->budget)
     return sfail(s, DDC_ENOMEM, "request needs %lld bytes, budget is %lld", (long long)bytes, (long long)s->budget);
   std::lock_guard<std::mutex> lk(s->mu);

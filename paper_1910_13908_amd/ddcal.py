@@ -67,6 +67,14 @@ class LMInfo(ct.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class LMStep(ct.Structure):
+    _fields_ = [("cost", ct.c_double), ("mu_eff", ct.c_double), ("mu", ct.c_double),
+                ("nu", ct.c_double), ("accepted", ct.c_int32), ("refine_steps", ct.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class CalOpts(ct.Structure):
     _fields_ = [("n_sweeps", ct.c_int32), ("lm", LMOpts)]
 
@@ -93,16 +101,17 @@ _lib.ddc_build_normal_eq.argtypes = [_vp, ct.POINTER(Obs), _vp, _vp, _vp, ct.c_i
 _lib.ddc_damped_solve.argtypes = [_vp, ct.c_int32, _vp, _vp, ct.c_double, ct.c_int32, ct.c_double,
                                   ct.c_int32, _vp, ct.POINTER(ct.c_int32)]
 _lib.ddc_lm_solve.argtypes = [_vp, ct.POINTER(Obs), _vp, _vp, _vp, ct.POINTER(LMOpts),
-                              ct.POINTER(LMState), ct.POINTER(LMInfo)]
+                              ct.POINTER(LMState), ct.POINTER(LMInfo), ct.POINTER(LMStep)]
 _lib.ddc_calibrate.argtypes = [_vp, ct.POINTER(Obs), ct.POINTER(Sky), _vp, _vp, ct.POINTER(CalOpts),
-                               _vp, ct.POINTER(LMInfo)]
+                               _vp, ct.POINTER(LMInfo), ct.POINTER(LMStep)]
 _lib.ddc_cost_gradient.argtypes = [_vp, ct.POINTER(Obs), ct.c_int32, _vp, _vp, _vp, ct.c_int32, _vp,
                                    ct.POINTER(ct.c_double)]
 _lib.ddc_enable_timing.argtypes = [_vp, ct.c_int32]
 _lib.ddc_enable_timers.argtypes = [_vp, ct.c_uint32]
 _lib.ddc_get_timing.argtypes = [_vp, ct.c_int32, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_double),
                                 ct.POINTER(ct.c_double)]
-_lib.ddc_calibrate_footprint.argtypes = [ct.POINTER(Obs), ct.c_int32, ct.c_int32, ct.c_int32]
+_lib.ddc_calibrate_footprint.argtypes = [ct.POINTER(Obs), ct.c_int32, ct.c_int32, ct.c_int32,
+                                         ct.c_int32]
 _lib.ddc_calibrate_footprint.restype = ct.c_int64
 _lib.ddc_server_create.argtypes = [ct.POINTER(_vp), ct.c_int32, ct.c_int32, ct.c_int64]
 _lib.ddc_server_destroy.argtypes = [_vp]
@@ -239,23 +248,40 @@ class Context:
         return d, steps.value
 
     def lm_solve(self, obs, y, coh_k, jones_k, opts: LMOpts, state: Optional[LMState] = None,
-                 want_info=True):
+                 want_info=True, want_trace=False):
+        """ddc_lm_solve; returns the LMInfo (or None), and with want_trace also the list of
+        per-iteration LMStep records."""
         info = LMInfo()
+        trace = (LMStep * max(1, opts.n_iter))() if want_trace else None
         self._bind()
         self._check(_lib.ddc_lm_solve(self.h, ct.byref(obs.c), _ptr(y), _ptr(coh_k), _ptr(jones_k),
                                       ct.byref(opts), ct.byref(state) if state is not None else None,
-                                      ct.byref(info) if want_info else None))
-        return info if want_info else None
+                                      ct.byref(info) if want_info else None, trace))
+        out = info if want_info else None
+        if want_trace:
+            return out, list(trace)[:opts.n_iter]
+        return out
 
-    def calibrate(self, obs, sky, vis, jones, n_sweeps, lm: LMOpts, res=None, want_info=True):
+    def calibrate(self, obs, sky, vis, jones, n_sweeps, lm: LMOpts, res=None, want_info=True,
+                  want_trace=False):
+        """ddc_calibrate; returns infos[sweep][cluster] (or None), and with want_trace also
+        trace[sweep][cluster] = list of per-iteration LMStep records."""
         opts = CalOpts(n_sweeps=n_sweeps, lm=lm)
         infos = (LMInfo * max(1, n_sweeps * sky.K))()
+        nit = lm.n_iter
+        trace = (LMStep * max(1, n_sweeps * sky.K * nit))() if want_trace else None
         self._bind()
         self._check(_lib.ddc_calibrate(self.h, ct.byref(obs.c), ct.byref(sky.c), _ptr(vis), _ptr(jones),
-                                       ct.byref(opts), _ptr(res), infos if want_info else None))
-        if not want_info:
-            return None
-        return [[infos[e * sky.K + k] for k in range(sky.K)] for e in range(n_sweeps)]
+                                       ct.byref(opts), _ptr(res), infos if want_info else None,
+                                       trace))
+        out = None
+        if want_info:
+            out = [[infos[e * sky.K + k] for k in range(sky.K)] for e in range(n_sweeps)]
+        if want_trace:
+            tr = [[list(trace[(e * sky.K + k) * nit:(e * sky.K + k + 1) * nit]) for k in range(sky.K)]
+                  for e in range(n_sweeps)]
+            return out, tr
+        return out
 
     def cost_gradient(self, obs, K, vis, coh, jones, precision, grad=None, want_cost=True):
         """f and df/d(jones) ([K, N, 8] float64) from the adjoint kernel."""
@@ -285,8 +311,10 @@ class Context:
         return n.value, ms.value, work.value
 
 
-def calibrate_footprint(obs: "DeviceObs", n_clusters: int, n_sweeps: int, precision: int) -> int:
-    return int(_lib.ddc_calibrate_footprint(ct.byref(obs.c), n_clusters, n_sweeps, precision))
+def calibrate_footprint(obs: "DeviceObs", n_clusters: int, n_sweeps: int, n_iter: int,
+                        precision: int) -> int:
+    return int(_lib.ddc_calibrate_footprint(ct.byref(obs.c), n_clusters, n_sweeps, n_iter,
+                                            precision))
 
 
 class Server:

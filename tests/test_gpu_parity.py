@@ -235,3 +235,34 @@ def test_invalid_arguments(dd, ctx):
     st = dd._lib.ddc_predict(ctx.h, ct.byref(d["obs"].c), None, 0, coh.data_ptr())
     assert st == dd.EINVAL
     assert b"sky" in dd._lib.ddc_last_error(ctx.h)
+
+
+# Polarised clusters, run to convergence.  SAGE's sweep is a Gauss-Seidel pass over the
+# clusters and converges only as fast as the clusters' models decouple over the sampled
+# baselines; on a few stations and timeslots with overlapping clusters it takes tens of
+# sweeps, and before its fixed point the GPU and oracle paths differ by whatever the path
+# amplifies.  These problems reach the fixed point: one cluster (LM alone), and two
+# clusters 20 degrees apart with 1-degree source spread over 20 sweeps.
+POL1 = synth.ObsConfig(16, 1, 4, 3, (150e6,), polarised=True, jones_amp=0.2)
+POL2 = synth.ObsConfig(16, 2, 4, 3, (150e6,), polarised=True, jones_amp=0.2,
+                       centre_radius_deg=20.0, source_radius_deg=1.0)
+
+
+@pytest.mark.parametrize("cfg, sweeps, n_lm", [(POL1, 1, 20), (POL2, 20, 10)], ids=["k1", "k2"])
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
+def test_calibrate_polarised_phase_only_gauge(dd, ctx, prec, cfg, sweeps, n_lm):
+    # polarised clusters (Q, U, V != 0) leave only a common phase free per cluster, so gains
+    # are compared after the phase-only alignment
+    import torch
+    ob, V, C = setup(cfg, seed=8)
+    J0 = synth.identity_jones(ob.K, ob.N)
+    Jo, Ro, io, _ = olm.calibrate(V, C, J0, ob.ant_p, ob.ant_q, n_sweeps=sweeps, n_lm=n_lm)
+    d = to_dev(dd, ob, prec, V=V)
+    Jd = torch.as_tensor(dd.jones_real(J0), device="cuda").contiguous()
+    infos = ctx.calibrate(d["obs"], d["sky"], d["V"], Jd, sweeps, dd.default_lm_opts(n_iter=n_lm, precision=prec))
+    Jg = dd.jones_complex(Jd.cpu().numpy())
+    tol_j, tol_c = (1e-8, 1e-9) if prec == 0 else (1e-4, 1e-5)
+    for k in range(ob.K):
+        e_phase = align.align_error(Jg[k], Jo[k], polarised=True)
+        assert e_phase <= tol_j, (k, e_phase)
+    assert abs(infos[-1][-1].cost - io[-1][-1].cost) <= tol_c * io[-1][-1].cost

@@ -175,8 +175,8 @@ def test_mu_floor(mu_rel, floor_active):
     mu_eff = max(mu, 1e-6 * md)
     assert (mu_eff > mu) == floor_active
     d, f, f_new, rho = _gain_ratio(ob, V, C, x0, r, A, mu_eff)
-    J1, info = lm.lm_solve(V, C, _x_to_J(x0), ob.ant_p, ob.ant_q, n_iter=1, mu=mu, nu=2.0,
-                           mu_floor=1e-6)
+    # called with the default floor: the reading is 1e-6 of max diag (the library's default)
+    J1, info = lm.lm_solve(V, C, _x_to_J(x0), ob.ant_p, ob.ant_q, n_iter=1, mu=mu, nu=2.0)
     assert info.accepted == [True]
     assert abs(info.mu_effs[0] - mu_eff) <= 1e-12 * mu_eff
     assert np.max(np.abs(_J_to_x(J1) - (x0 + d))) <= 1e-8 * np.max(np.abs(d))

@@ -175,6 +175,20 @@ ddc_status ddc_residual(ddc_ctx* ctx, const ddc_obs* obs, int32_t n_clusters, co
                         const void* coh, const double* jones, int32_t precision,
                         void* res, double* cost);
 
+/* ddc_residual for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same arguments,
+ * kernels and results, bit for bit, with the call's scratch (canonical baseline table and
+ * per-workgroup cost partials, 1.5 MiB) in a fixed device array that each GPU holds for the
+ * life of the process, instead of the context workspace.  The call allocates nothing
+ * (no hipMalloc/hipFree, no workspace growth).  Limits: n_stations <= 512 and
+ * n_times * n_chans * N(N-1)/2 <= 16777216; beyond them DDC_EINVAL.  Every call on one GPU
+ * shares that array (each call rebuilds what it reads from it first), so calls that overlap
+ * on one GPU race: serialise them on one stream.  With cost (HOST) non-NULL the call
+ * synchronises the stream; DDC_ENONFINITE as for ddc_residual. */
+ddc_status ddc_residual_noalloc(ddc_ctx* ctx, const ddc_obs* obs, int32_t n_clusters,
+                                const void* vis, const void* coh, const double* jones,
+                                int32_t precision, void* res, double* cost);
+
 /* out = in + alpha * sum_{k<K} J_k C_k J_k^H (alpha = +1 or -1); out may alias in: the
  * model of clusters 0..K-1 (paper Section 2, one Jones solution per cluster) added to or
  * taken from visibility planes.  Used to form synthetic data (in = noise) and the

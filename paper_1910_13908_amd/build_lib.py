@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libddcal.so")
 SOURCES = ["ddcal.cpp", "server.cpp", "k_predict.hip", "k_predict_factored.hip", "k_vis.hip",
-           "k_chol.hip", "k_lm.hip"]
+           "k_chol.hip", "k_lm.hip", "noalloc.hip"]
 ARCH = os.environ.get("DDC_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are kept out of the generated code.

@@ -176,6 +176,22 @@ hipError_t launch_refine_resid(const R* Hc, int ld, int n_pad, const double* mu_
                                SyncArea* sync, double tol2, hipStream_t st);
 hipError_t set_chol_smem_attr();
 
+// noalloc.hip: the fixed device scratch of the entry point that allocates nothing.
+constexpr int kNoAllocMaxStations = 512;
+constexpr int64_t kNoAllocMaxBaselines = (int64_t)kNoAllocMaxStations * (kNoAllocMaxStations - 1) / 2;
+constexpr int64_t kNoAllocMaxBlocks = 65536;   // cost partials: T*F*B <= 65536 * 256
+struct NoAllocScratch {
+  int32_t* ant;     // [2][B] canonical baseline table (rebuilt by every call)
+  double* parts;    // [kNoAllocMaxBlocks] per-workgroup cost partials
+  double* total;    // the cost
+};
+// Looks up the scratch array's address on `device` (which must be current), once per device.
+hipError_t noalloc_setup(int device);
+// The looked-up scratch of `device` (all null before noalloc_setup succeeded on it).
+NoAllocScratch noalloc_scratch(int device);
+hipError_t launch_baseline_table(int N, int64_t B, int32_t* ant_p, int32_t* ant_q,
+                                 hipStream_t st);
+
 // k_lm.hip
 hipError_t launch_lm_init(LMState* st, int fresh, double mu, double nu, hipStream_t s);
 hipError_t launch_lm_pre(LMState* st, const double* cost_part, int nblk, const double* diag,

@@ -432,7 +432,8 @@ ddc_status ddc_create(ddc_ctx** out, int32_t device) {
   if (hipMalloc(&c->sync, kSyncBytes) != hipSuccess ||
       hipMemset(c->sync, 0, 1u << 20) != hipSuccess ||
       launch_fill_empty(c->solve_psum(), 2 * 64 * kMaxTiles + kMaxTiles, nullptr) != hipSuccess ||
-      set_chol_smem_attr() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+      set_chol_smem_attr() != hipSuccess || noalloc_setup(device) != hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess) {
     (void)hipGetLastError();
     if (c->sync) (void)hipFree(c->sync);
     delete c;
@@ -598,6 +599,59 @@ ddc_status ddc_residual(ddc_ctx* c, const ddc_obs* obs, int32_t K, const void* v
   if (!res && !cost) return DDC_OK;
   if (prec == DDC_MIXED) return add_model_impl<float>(c, o, K, vis, coh, jones, -1.0, res, cost);
   return add_model_impl<double>(c, o, K, vis, coh, jones, -1.0, res, cost);
+}
+
+ddc_status ddc_residual_noalloc(ddc_ctx* c, const ddc_obs* obs, int32_t K, const void* vis,
+                                const void* coh, const double* jones, int32_t prec, void* res,
+                                double* cost) {
+  if (!c) return DDC_EINVAL;
+  (void)hipSetDevice(c->device);
+  DDCCK(check_obs(c, obs));
+  DDCCK(check_prec(c, prec));
+  if (K < 1 || !vis || !coh || !jones) return fail(c, DDC_EINVAL, "bad residual arguments");
+  if (obs->n_stations > kNoAllocMaxStations)
+    return fail(c, DDC_EINVAL, "n_stations %d exceeds the no-allocation limit of %d",
+                obs->n_stations, kNoAllocMaxStations);
+  const int64_t B = (int64_t)obs->n_stations * (obs->n_stations - 1) / 2;
+  const int64_t plane = (int64_t)obs->n_times * obs->n_chans * B;
+  if ((plane + 255) / 256 > kNoAllocMaxBlocks)
+    return fail(c, DDC_EINVAL, "%lld visibilities per plane exceed the no-allocation limit of %lld",
+                (long long)plane, (long long)(kNoAllocMaxBlocks * 256));
+  if (!res && !cost) return DDC_OK;
+  const NoAllocScratch sc = noalloc_scratch(c->device);
+  if (!sc.ant) return fail(c, DDC_EDEVICE, "no-allocation scratch not set up on device %d", c->device);
+  // the baseline table lives in the scratch too (the context's own table may need an
+  // allocation when N changes), rebuilt by every call
+  ObsDev o;
+  o.N = obs->n_stations;
+  o.T = obs->n_times;
+  o.F = obs->n_chans;
+  o.B = B;
+  o.u = obs->u;
+  o.v = obs->v;
+  o.w = obs->w;
+  o.freq = obs->freq_hz;
+  o.ant_p = sc.ant;
+  o.ant_q = sc.ant + B;
+  hipStream_t st = c->stream;
+  HIPCK(launch_baseline_table(o.N, B, sc.ant, sc.ant + B, st));
+  double* parts = cost ? sc.parts : nullptr;
+  int nb = 0;
+  if (prec == DDC_MIXED)
+    HIPCK(launch_add_model<float>(o, 0, K, reinterpret_cast<const float*>(vis),
+                                  reinterpret_cast<const float*>(coh), jones, -1.0,
+                                  reinterpret_cast<float*>(res), parts, &nb, st));
+  else
+    HIPCK(launch_add_model<double>(o, 0, K, reinterpret_cast<const double*>(vis),
+                                   reinterpret_cast<const double*>(coh), jones, -1.0,
+                                   reinterpret_cast<double*>(res), parts, &nb, st));
+  if (cost) {
+    HIPCK(launch_sum(parts, nb, sc.total, st));
+    HIPCK(hipMemcpyAsync(cost, sc.total, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCK(hipStreamSynchronize(st));
+    if (!std::isfinite(*cost)) return fail(c, DDC_ENONFINITE, "the cost is not finite");
+  }
+  return DDC_OK;
 }
 
 ddc_status ddc_add_model(ddc_ctx* c, const ddc_obs* obs, int32_t K, const void* in,

@@ -32,7 +32,8 @@ OK, EINVAL, ENOMEM, EDEVICE, ENOTPD, ENONFINITE, ETIMEOUT = 0, -1, -2, -3, -4, -
  TIMER_ADJOINT, TIMER_PREDICT_FACTORED) = range(9)
 
 EXPORTS = ("ddc_default_lm_opts", "ddc_create", "ddc_destroy", "ddc_set_stream", "ddc_last_error",
-           "ddc_workspace_bytes", "ddc_predict", "ddc_predict_factored", "ddc_residual", "ddc_add_model",
+           "ddc_workspace_bytes", "ddc_predict", "ddc_predict_factored", "ddc_residual",
+           "ddc_residual_noalloc", "ddc_add_model",
            "ddc_build_normal_eq", "ddc_damped_solve", "ddc_lm_solve", "ddc_calibrate",
            "ddc_cost_gradient", "ddc_enable_timing", "ddc_enable_timers", "ddc_get_timing", "ddc_calibrate_footprint",
            "ddc_server_create", "ddc_server_destroy", "ddc_server_submit", "ddc_server_wait",
@@ -94,6 +95,8 @@ _lib.ddc_predict_factored.argtypes = [_vp, ct.POINTER(Obs), _vp, _vp, _vp, ct.PO
                                       ct.c_int32, _vp]
 _lib.ddc_residual.argtypes = [_vp, ct.POINTER(Obs), ct.c_int32, _vp, _vp, _vp, ct.c_int32, _vp,
                               ct.POINTER(ct.c_double)]
+_lib.ddc_residual_noalloc.argtypes = [_vp, ct.POINTER(Obs), ct.c_int32, _vp, _vp, _vp, ct.c_int32,
+                                      _vp, ct.POINTER(ct.c_double)]
 _lib.ddc_add_model.argtypes = [_vp, ct.POINTER(Obs), ct.c_int32, _vp, _vp, _vp, ct.c_double,
                                ct.c_int32, _vp]
 _lib.ddc_build_normal_eq.argtypes = [_vp, ct.POINTER(Obs), _vp, _vp, _vp, ct.c_int32, _vp, _vp,
@@ -215,6 +218,15 @@ class Context:
         cost = ct.c_double(0.0)
         self._check(_lib.ddc_residual(self.h, ct.byref(obs.c), K, _ptr(vis), _ptr(coh), _ptr(jones),
                                       precision, _ptr(res), ct.byref(cost) if want_cost else None))
+        return cost.value if want_cost else None
+
+    def residual_noalloc(self, obs, K, vis, coh, jones, precision, res=None, want_cost=True):
+        """ddc_residual_noalloc: ddc_residual with fixed device scratch (no allocation)."""
+        self._bind()
+        cost = ct.c_double(0.0)
+        self._check(_lib.ddc_residual_noalloc(self.h, ct.byref(obs.c), K, _ptr(vis), _ptr(coh),
+                                              _ptr(jones), precision, _ptr(res),
+                                              ct.byref(cost) if want_cost else None))
         return cost.value if want_cost else None
 
     def add_model(self, obs, K, inp, coh, jones, alpha, precision, out):

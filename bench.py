@@ -43,9 +43,14 @@ def parse():
                          "runtime over the station-count x cluster-count grid")
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--slots", type=int, default=4)
-    ap.add_argument("--with-serve", action="store_true",
-                    help="also measure the served stream in the lm mode")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the served stream (mixed and FP64) in the lm mode")
     return ap.parse_args()
+
+
+def _progress(msg):
+    """Progress line on stderr (stdout carries only the JSON result)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def _percentile(xs, q):
@@ -90,8 +95,9 @@ def serve_measure(n_requests=200, n_slots=4, seed=0, precision="mixed"):
     budget = int(n_slots * foot * 1.05) + (64 << 20)
     srv = dd.Server(0, n_slots=n_slots, hbm_budget_bytes=budget)
 
-    def run(arrivals):
-        for r in reqs:
+    def run(arrivals, subset=None):
+        rs = reqs if subset is None else reqs[:subset]
+        for r in rs:
             r["J"].copy_(r["J0"])
         torch.cuda.synchronize()
         q = queue.Queue()
@@ -108,7 +114,7 @@ def serve_measure(n_requests=200, n_slots=4, seed=0, precision="mixed"):
         th = threading.Thread(target=collector)
         th.start()
         t0 = time.perf_counter()
-        for r, ta in zip(reqs, arrivals):
+        for r, ta in zip(rs, arrivals):
             dtw = t0 + ta - time.perf_counter()
             if dtw > 0:
                 time.sleep(dtw)
@@ -117,11 +123,12 @@ def serve_measure(n_requests=200, n_slots=4, seed=0, precision="mixed"):
         q.put(None)
         th.join()
         el = time.perf_counter() - t0
-        return {"solves_per_s": len(reqs) / el, "p50_latency_s": _percentile(lat, 0.5),
+        return {"solves_per_s": len(rs) / el, "p50_latency_s": _percentile(lat, 0.5),
                 "p99_latency_s": _percentile(lat, 0.99), "elapsed_s": el}
 
-    run(np.zeros(len(reqs)))                 # warm-up pass (workspaces, code objects)
+    run(np.zeros(len(reqs)), subset=24)      # warm-up pass (code objects, every request shape)
     closed = run(np.zeros(len(reqs)))
+    _progress(f"serve {precision}: closed loop {closed['solves_per_s']:.2f} solves/s")
     sat = closed["solves_per_s"]
     out = {"requests": len(reqs), "slots": n_slots, "arena_bytes": budget,
            "mix": "N in {64,128,256,384,512}, K in {1,5,10,20} x 20 sources, T=10, F=1",
@@ -129,6 +136,7 @@ def serve_measure(n_requests=200, n_slots=4, seed=0, precision="mixed"):
     for frac in (0.5, 0.9):
         arr = synth.poisson_arrivals(frac * sat, len(reqs), seed=seed + 7)
         out[f"poisson_{frac}x"] = dict(run(arr), rate_hz=frac * sat)
+        _progress(f"serve {precision}: Poisson {frac}x p50 {out[f'poisson_{frac}x']['p50_latency_s']:.3f} s")
     out["server"] = srv.stats()
     srv.close()
     return out
@@ -182,13 +190,13 @@ def lbfgs_measure(seed=0, n_iter=200):
     return out
 
 
-def scan_measure(seed=0, n_lm=10, oracle_max_n=128):
+def scan_measure(seed=0, n_lm=10, oracle_max_n=512):
     """Calibration runtime over the paper's station grid and cluster counts (its runtime-vs-N
     and runtime-vs-K experiments, Section 3): N in {64, 128, 256, 384, 512} x K in
     {1, 5, 10, 20, 50} clusters of 20 sources, T=10, F=1, one SAGE sweep of n_lm LM iterations
     per cluster, mixed and FP64.  The time covers predict + calibrate with data resident in
-    HBM.  The CPU line is the FP64 oracle's time for one LM iteration of one cluster, for
-    N <= oracle_max_n (larger N take minutes per iteration on the host)."""
+    HBM.  The CPU line is the FP64 oracle's time for one LM iteration of one cluster (at K = 1,
+    for N <= oracle_max_n; seconds per iteration at N = 512)."""
     import torch
     from paper_1910_13908_amd import synth, ddcal as dd
     ctx = dd.Context(0)
@@ -393,6 +401,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
+    _progress(f"{args.steps} timed steps: {elapsed:.1f} s")
     timer_names = ["cholesky", "predict", "build", "trsv", "trial", "model", "refine", "adjoint"]
     timers = {name: ctx.timing(i) for i, name in enumerate(timer_names)}
     # one more step with every kernel class timed: the per-kernel breakdown, and the LM info
@@ -468,7 +477,7 @@ def main():
     torch.cuda.empty_cache()
 
     if prec == dd.MIXED and not args.no_fp64_compare:
-        del V
+        V = None
         torch.cuda.empty_cache()
         V64 = make_vis(dd.FP64, torch.float64)
         J64 = J0.clone()
@@ -480,11 +489,25 @@ def main():
         ctx.calibrate(obs, sky, V64, J64, cfg.n_sweeps, lm64, want_info=False)
         torch.cuda.synchronize()
         out["fp64_path_lm_iters_per_s"] = n_lm_per_step / (time.perf_counter() - t0)
+        V64 = None
+        _progress("FP64 path timed")
 
-    if args.with_serve:
-        out["served"] = serve_measure(args.requests, args.slots, args.seed, args.precision)
+    if not args.no_serve:
+        # the served stream of calibration requests, in both precisions: solves/s at
+        # saturation (all requests at t = 0) and p50/p99 latency under Poisson arrivals at
+        # 0.5x and 0.9x that rate
+        V = None
+        torch.cuda.empty_cache()
+        served = {}
+        for p in ("mixed", "fp64"):
+            served[p] = serve_measure(args.requests, args.slots, args.seed, p)
+            torch.cuda.empty_cache()
+        served["mixed_over_fp64_solves_per_s"] = (served["mixed"]["closed_loop"]["solves_per_s"] /
+                                                  served["fp64"]["closed_loop"]["solves_per_s"])
+        out["served"] = served
 
     if not args.no_cpu_baseline:
+        _progress("oracle on the host")
         out["cpu_baseline"] = cpu_baseline(cfg, args.seed)
 
     print(json.dumps(out), flush=True)

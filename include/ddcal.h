@@ -143,7 +143,7 @@ int64_t ddc_workspace_bytes(const ddc_ctx* ctx);
 
 /* Model coherencies of every cluster (the predict of the measurement equation above).
  * coh: [K][8][T][F][B] of the precision's element type.  The phase argument is always
- * evaluated in FP64 and reduced to [-1/2, 1/2) turns; DDC_MIXED then takes FP32 sin/cos
+ * evaluated in FP64 and reduced to its fractional part, [0, 1) turns; DDC_MIXED takes FP32 sin/cos
  * and accumulates in FP32, DDC_FP64 stays in double.  Paper Section 2 (clusters) and
  * Section 3 (baselines). */
 ddc_status ddc_predict(ddc_ctx* ctx, const ddc_obs* obs, const ddc_sky* sky,

@@ -90,8 +90,10 @@ inline PredictJob make_predict_job(const ObsDev& o, int K, const int32_t* offs_d
   return j;
 }
 
+// Work items of one job in the batched predict: 256-baseline tiles x (timeslot, channel);
+// each item covers every cluster.
 inline int64_t predict_blocks(const PredictJob& j) {
-  return (j.B + 255) / 256 * (int64_t)j.T * j.F * j.K;
+  return (j.B + 255) / 256 * (int64_t)j.T * j.F;
 }
 
 // k_predict.hip

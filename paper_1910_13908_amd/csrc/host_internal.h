@@ -27,8 +27,10 @@ int64_t calibrate_footprint(const ObsDev& o, int K, int n_sweeps, int n_iter, in
 ddc_status prepare_calibrate(ddc_ctx* c, const ObsDev& o, const ddc_sky* sky, int n_sweeps,
                              int n_iter, int prec, CalBufs& cb);
 void release_calibrate(CalBufs& cb);
+// The SAGE sweeps of one calibration; residual_ready: cb.Rb already holds V - sum_k J_k C_k J_k^H
+// (formed by a batched launch), otherwise it is formed first.
 ddc_status enqueue_sage(ddc_ctx* c, const ObsDev& o, const void* vis, double* jones,
-                        const ddc_cal_opts& opt, CalBufs& cb);
+                        const ddc_cal_opts& opt, CalBufs& cb, bool residual_ready = false);
 // Reads every visit's state back; info and trace (HOST, nullable) receive the reports.
 ddc_status collect_infos(ddc_ctx* c, CalBufs& cb, ddc_lm_info* info, ddc_lm_step* trace);
 ddc_status ctx_obs(ddc_ctx* c, const ddc_obs* obs, ObsDev& o);

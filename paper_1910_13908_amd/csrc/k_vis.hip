@@ -137,6 +137,37 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 // ---------------------------------------------------------------------------------------
 // out = in + alpha * sum_{k in [k0,k1)} J_k C_k J_k^H; optional cost partials of ||out||^2.
 // ---------------------------------------------------------------------------------------
+// One element i of out = in + alpha * sum_k J_k C_k J_k^H; returns ||out_i||^2.  Shared by
+// the single-problem kernel and the batched one, so both round identically.
+template <typename R>
+__device__ __forceinline__ double add_model_elem(
+    const R* __restrict__ in, const R* __restrict__ coh, const double* __restrict__ jones,
+    const int32_t* __restrict__ ant_p, const int32_t* __restrict__ ant_q, int64_t B,
+    int64_t plane, int N, int k0, int k1, R alpha, R* __restrict__ out, int64_t i) {
+  const int64_t b = i % B;
+  const int p = ant_p[b], q = ant_q[b];
+  M2<R> acc = load_vis(in, plane, i);
+  for (int k = k0; k < k1; ++k) {
+    const M2<R> Jp = load_jones<R>(jones + (int64_t)k * 8 * N, p);
+    const M2<R> Jq = load_jones<R>(jones + (int64_t)k * 8 * N, q);
+    const M2<R> C = load_vis(coh + (int64_t)k * 8 * plane, plane, i);
+    const M2<R> M = mmul_bh(mmul(Jp, C), Jq);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      acc.e[e].r = fma(alpha, M.e[e].r, acc.e[e].r);
+      acc.e[e].i = fma(alpha, M.e[e].i, acc.e[e].i);
+    }
+  }
+  if (out) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      out[(2 * e) * plane + i] = acc.e[e].r;
+      out[(2 * e + 1) * plane + i] = acc.e[e].i;
+    }
+  }
+  return norm2(acc);
+}
+
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_add_model(
     const R* __restrict__ in, const R* __restrict__ coh, const double* __restrict__ jones,
@@ -146,33 +177,28 @@ __global__ __launch_bounds__(kThreads) void k_add_model(
   __shared__ double sh[kThreads / 64];
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   double cst = 0.0;
-  if (i < plane) {
-    const int64_t b = i % B;
-    const int p = ant_p[b], q = ant_q[b];
-    M2<R> acc = load_vis(in, plane, i);
-    for (int k = k0; k < k1; ++k) {
-      const M2<R> Jp = load_jones<R>(jones + (int64_t)k * 8 * N, p);
-      const M2<R> Jq = load_jones<R>(jones + (int64_t)k * 8 * N, q);
-      const M2<R> C = load_vis(coh + (int64_t)k * 8 * plane, plane, i);
-      const M2<R> M = mmul_bh(mmul(Jp, C), Jq);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        acc.e[e].r = fma(alpha, M.e[e].r, acc.e[e].r);
-        acc.e[e].i = fma(alpha, M.e[e].i, acc.e[e].i);
-      }
-    }
-    if (out) {
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        out[(2 * e) * plane + i] = acc.e[e].r;
-        out[(2 * e + 1) * plane + i] = acc.e[e].i;
-      }
-    }
-    cst = norm2(acc);
-  }
+  if (i < plane) cst = add_model_elem<R>(in, coh, jones, ant_p, ant_q, B, plane, N, k0, k1, alpha, out, i);
   if (cost_part) {
     const double s = block_sum(cst, sh);
     if (threadIdx.x == 0) cost_part[blockIdx.x] = s;
+  }
+}
+
+// Initial residuals of several solves in one persistent launch: the workgroups walk the
+// flattened list of (job, 256-element block) items with a grid stride; each element runs
+// add_model_elem with every cluster and alpha = -1, as k_add_model does for one solve.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_residual_batch(const ResidualJob* __restrict__ jobs,
+                                                            int njobs, int64_t total) {
+  for (int64_t vb = blockIdx.x; vb < total; vb += gridDim.x) {
+    int jj = 0;
+    while (jj + 1 < njobs && jobs[jj + 1].first_block <= vb) ++jj;
+    const ResidualJob& j = jobs[jj];
+    const int64_t i = (vb - j.first_block) * kThreads + threadIdx.x;
+    if (i < j.plane)
+      (void)add_model_elem<R>(reinterpret_cast<const R*>(j.vis), reinterpret_cast<const R*>(j.coh),
+                              j.jones, j.ant_p, j.ant_q, j.B, j.plane, j.N, 0, j.K, (R)-1,
+                              reinterpret_cast<R*>(j.out), i);
   }
 }
 
@@ -484,6 +510,16 @@ hipError_t launch_add_model(const ObsDev& o, int k0, int k1, const R* in, const 
   return hipGetLastError();
 }
 
+template <typename R>
+hipError_t launch_residual_batch(const ResidualJob* jobs_dev, int njobs, int64_t total_blocks,
+                                 int grid, hipStream_t st) {
+  if (total_blocks <= 0) return hipSuccess;
+  const int g = (int)(total_blocks < grid ? total_blocks : grid);
+  hipLaunchKernelGGL(k_residual_batch<R>, dim3(g), dim3(kThreads), 0, st, jobs_dev, njobs,
+                     total_blocks);
+  return hipGetLastError();
+}
+
 hipError_t launch_sum(const double* parts, int n, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_sum, dim3(1), dim3(kThreads), 0, st, parts, n, out);
   return hipGetLastError();
@@ -531,6 +567,8 @@ hipError_t launch_cost_adjoint(const ObsDev& o, int K, const R* res, const R* co
 }
 
 #define DDC_INST(R)                                                                          \
+  template hipError_t launch_residual_batch<R>(const ResidualJob*, int, int64_t, int,          \
+                                               hipStream_t);                                   \
   template hipError_t launch_add_model<R>(const ObsDev&, int, int, const R*, const R*,        \
                                           const double*, double, R*, double*, int*,           \
                                           hipStream_t);                                       \

@@ -8,9 +8,9 @@
 //   * each admitted request occupies one slot: a library context with its own HIP stream
 //     whose workspace is lent from the arena, so solves of different sizes run side by side
 //     and their kernels overlap on the device;
-//   * the predict work of every request admitted in the same scheduling round is fused into
-//     one persistent batched launch on a shared stream, which the slots' streams wait on
-//     before their SAGE sweeps start.
+//   * the predict and the initial residual (R = V - sum_k J_k C_k J_k^H) of every request
+//     admitted in the same scheduling round are fused into persistent batched launches on a
+//     shared stream, which the slots' streams wait on before their SAGE sweeps start.
 // One scheduler thread owns every HIP call of the server; submit/wait only touch the
 // request table.  All reductions in the path have a fixed order, so a solve's result does
 // not depend on what else is running (bitwise).
@@ -68,8 +68,10 @@ struct Slot {
 
 struct JobBuf {
   PredictJob* dev = nullptr;
+  ResidualJob* rdev = nullptr;
   hipEvent_t used = nullptr;
   std::vector<PredictJob> host;
+  std::vector<ResidualJob> rhost;
   bool pending = false;
 };
 
@@ -189,8 +191,10 @@ void retire(ddc_server* s, bool& any) {
   }
 }
 
+// One batched predict over the jobs, then one batched initial residual of the same requests
+// (which reads the coherencies the predict wrote), both on the batch stream.
 template <typename R>
-hipError_t launch_batch(ddc_server* s, std::vector<PredictJob>& jobs) {
+hipError_t launch_batch(ddc_server* s, std::vector<PredictJob>& jobs, std::vector<ResidualJob>& rjobs) {
   if (jobs.empty()) return hipSuccess;
   JobBuf& jb = s->ring[s->ring_next];
   s->ring_next = (s->ring_next + 1) % kJobRing;
@@ -203,11 +207,22 @@ hipError_t launch_batch(ddc_server* s, std::vector<PredictJob>& jobs) {
     j.first_block = total;
     total += predict_blocks(j);
   }
+  int64_t rtotal = 0;
+  for (auto& j : rjobs) {
+    j.first_block = rtotal;
+    rtotal += residual_blocks(j);
+  }
   jb.host = jobs;
+  jb.rhost = rjobs;
   hipError_t e = hipMemcpyAsync(jb.dev, jb.host.data(), jobs.size() * sizeof(PredictJob),
                                 hipMemcpyHostToDevice, s->batch_stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(jb.rdev, jb.rhost.data(), rjobs.size() * sizeof(ResidualJob),
+                       hipMemcpyHostToDevice, s->batch_stream);
   if (e != hipSuccess) return e;
   e = launch_predict_batch<R>(jb.dev, (int)jobs.size(), total, s->grid, s->batch_stream);
+  if (e != hipSuccess) return e;
+  e = launch_residual_batch<R>(jb.rdev, (int)rjobs.size(), rtotal, s->grid, s->batch_stream);
   if (e != hipSuccess) return e;
   e = hipEventRecord(jb.used, s->batch_stream);
   jb.pending = true;
@@ -248,6 +263,7 @@ void admit(ddc_server* s, bool& any) {
   if (admitted.empty()) return;
   any = true;
   std::vector<PredictJob> jobs32, jobs64;
+  std::vector<ResidualJob> res32, res64;
   std::vector<std::pair<int, int64_t>> started;
   for (auto& a : admitted) {
     Slot& sl = s->slots[a.first];
@@ -274,17 +290,35 @@ void admit(ddc_server* s, bool& any) {
     }
     PredictJob j = make_predict_job(r->od, r->sky.n_clusters, r->cb.doffs, r->sky.l, r->sky.m,
                                     r->sky.I, r->sky.Q, r->sky.U, r->sky.V, r->cb.coh);
-    (r->opts.lm.precision == DDC_MIXED ? jobs32 : jobs64).push_back(j);
+    ResidualJob rj;
+    rj.vis = r->vis;
+    rj.coh = r->cb.coh;
+    rj.jones = r->jones;
+    rj.ant_p = r->od.ant_p;
+    rj.ant_q = r->od.ant_q;
+    rj.out = r->cb.Rb;
+    rj.B = r->od.B;
+    rj.plane = (int64_t)r->od.T * r->od.F * r->od.B;
+    rj.N = r->od.N;
+    rj.K = r->sky.n_clusters;
+    rj.first_block = 0;
+    const bool mixed = r->opts.lm.precision == DDC_MIXED;
+    (mixed ? jobs32 : jobs64).push_back(j);
+    (mixed ? res32 : res64).push_back(rj);
     started.push_back(a);
   }
   hipError_t e = hipSuccess;
   for (size_t i = 0; i < jobs32.size() && e == hipSuccess; i += kMaxJobsPerBatch) {
-    std::vector<PredictJob> part(jobs32.begin() + i, jobs32.begin() + std::min(jobs32.size(), i + kMaxJobsPerBatch));
-    e = launch_batch<float>(s, part);
+    const size_t i1 = std::min(jobs32.size(), i + kMaxJobsPerBatch);
+    std::vector<PredictJob> part(jobs32.begin() + i, jobs32.begin() + i1);
+    std::vector<ResidualJob> rpart(res32.begin() + i, res32.begin() + i1);
+    e = launch_batch<float>(s, part, rpart);
   }
   for (size_t i = 0; i < jobs64.size() && e == hipSuccess; i += kMaxJobsPerBatch) {
-    std::vector<PredictJob> part(jobs64.begin() + i, jobs64.begin() + std::min(jobs64.size(), i + kMaxJobsPerBatch));
-    e = launch_batch<double>(s, part);
+    const size_t i1 = std::min(jobs64.size(), i + kMaxJobsPerBatch);
+    std::vector<PredictJob> part(jobs64.begin() + i, jobs64.begin() + i1);
+    std::vector<ResidualJob> rpart(res64.begin() + i, res64.begin() + i1);
+    e = launch_batch<double>(s, part, rpart);
   }
   if (e == hipSuccess) e = hipEventRecord(s->batch_ev, s->batch_stream);
   for (auto& a : started) {
@@ -296,7 +330,7 @@ void admit(ddc_server* s, bool& any) {
     }
     ddc_status st = e == hipSuccess ? DDC_OK : DDC_EDEVICE;
     if (st == DDC_OK && hipStreamWaitEvent(sl.stream, s->batch_ev, 0) != hipSuccess) st = DDC_EDEVICE;
-    if (st == DDC_OK) st = host::enqueue_sage(sl.ctx, r->od, r->vis, r->jones, r->opts, r->cb);
+    if (st == DDC_OK) st = host::enqueue_sage(sl.ctx, r->od, r->vis, r->jones, r->opts, r->cb, true);
     if (st == DDC_OK && hipEventRecord(sl.done, sl.stream) != hipSuccess) st = DDC_EDEVICE;
     if (st != DDC_OK) {
       // the request's predict may already be queued on the batch stream, writing into its
@@ -392,6 +426,7 @@ ddc_status ddc_server_create(ddc_server** out, int32_t device, int32_t n_slots,
             hipEventCreateWithFlags(&s->batch_ev, hipEventDisableTiming) == hipSuccess;
   for (auto& jb : s->ring) {
     ok = ok && hipMalloc(&jb.dev, kMaxJobsPerBatch * sizeof(PredictJob)) == hipSuccess &&
+         hipMalloc(&jb.rdev, kMaxJobsPerBatch * sizeof(ResidualJob)) == hipSuccess &&
          hipEventCreateWithFlags(&jb.used, hipEventDisableTiming) == hipSuccess;
   }
   s->slots.resize(n_slots);
@@ -433,6 +468,7 @@ ddc_status ddc_server_destroy(ddc_server* s) {
   if (s->batch_stream) (void)hipStreamSynchronize(s->batch_stream);
   for (auto& jb : s->ring) {
     if (jb.dev) (void)hipFree(jb.dev);
+    if (jb.rdev) (void)hipFree(jb.rdev);
     if (jb.used) (void)hipEventDestroy(jb.used);
   }
   if (s->batch_ev) (void)hipEventDestroy(s->batch_ev);

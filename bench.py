@@ -525,6 +525,29 @@ def main():
     out["predict_factored_us"] = 1e3 * ms_pf / max(n_pf, 1)
     torch.cuda.empty_cache()
 
+    # the residual kernel on its own (ddc_residual: R = V - sum_k J_k C_k J_k^H over all K
+    # clusters at the calibrated Jones, with the cost): its algorithmic bytes are the data,
+    # K coherency planes and the residual written, (16 + 8K) elements per visibility
+    coh = ctx.predict(obs, sky, prec)
+    Rres = torch.empty_like(V)
+    ctx.residual(obs, K, V, coh, J, prec, res=Rres)
+    torch.cuda.synchronize()
+    ctx.enable_timing(True, timers=[dd.TIMER_MODEL])
+    for _ in range(5):
+        ctx.residual(obs, K, V, coh, J, prec, res=Rres, want_cost=False)
+    n_rs, ms_rs, _ = ctx.timing(dd.TIMER_MODEL)
+    ctx.enable_timing(False)
+    es = 4 if prec == dd.MIXED else 8
+    res_bytes = (16 + 8 * K) * es * ob.B * ob.T * ob.F
+    out["roofline_residual"] = {
+        "bound": "hbm", "kernel": "k_add_model (ddc_residual, all clusters)", "unit": "GB/s",
+        "peak": PEAK["hbm_gbs"], "achieved": n_rs * res_bytes / (ms_rs * 1e-3) / 1e9,
+        "frac": n_rs * res_bytes / (ms_rs * 1e-3) / 1e9 / PEAK["hbm_gbs"],
+        "avg_us": 1e3 * ms_rs / max(n_rs, 1), "traffic": None,
+        "per_launch": f"(16 + 8K) x {es} B x {ob.B * ob.T * ob.F} visibilities = {res_bytes / 1e6:.1f} MB"}
+    del coh, Rres
+    torch.cuda.empty_cache()
+
     if prec == dd.MIXED and not args.no_fp64_compare:
         V = None
         torch.cuda.empty_cache()

@@ -314,6 +314,12 @@ typedef enum {
   DDC_TIMER_PREDICT_FACTORED = 8  /* station-factorised predict; work = coherencies (K*T*F*B) */
 } ddc_timer;
 ddc_status ddc_enable_timing(ddc_ctx* ctx, int32_t on);
+/* Bound every inter-workgroup wait of the context's factorisations and solves at `polls`
+ * polls (0 restores the default, 2^22 polls, about a second).  Every such wait is bounded;
+ * this makes the bound small so that the timeout path can be exercised: the factorisation or
+ * solve that exceeds it aborts (all its workgroups leave), the LM step is rejected, and
+ * ddc_lm_solve / ddc_calibrate / ddc_damped_solve report DDC_ETIMEOUT.  Synchronises. */
+ddc_status ddc_set_wait_limit(ddc_ctx* ctx, uint32_t polls);
 /* Time only the kernel classes whose bit (1 << ddc_timer) is set in mask (0: none).  Each
  * bracketing event pair adds a stream marker that waits for the launch before it, so a
  * throughput measurement times only the kernels it reports.  Resets the totals like

@@ -1078,6 +1078,15 @@ ddc_status ddc_enable_timers(ddc_ctx* c, uint32_t mask) {
   return DDC_OK;
 }
 
+ddc_status ddc_set_wait_limit(ddc_ctx* c, uint32_t polls) {
+  if (!c) return DDC_EINVAL;
+  (void)hipSetDevice(c->device);
+  HIPCK(hipStreamSynchronize(c->stream));
+  for (int i = 0; i < 4; ++i)
+    HIPCK(hipMemcpy(&c->area(i)->pad, &polls, sizeof polls, hipMemcpyHostToDevice));
+  return DDC_OK;
+}
+
 ddc_status ddc_enable_timing(ddc_ctx* c, int32_t on) {
   return ddc_enable_timers(c, on ? 0xffffffffu : 0u);
 }

@@ -45,6 +45,13 @@ namespace {
 constexpr int kThreads = 256;
 constexpr uint32_t kSpinLimit = 1u << 22;   // polls (with s_sleep) before a wait gives up
 
+// The bound of every wait of a launch: the host may lower it through the sync area's spare
+// word (ddc_set_wait_limit, to exercise the timeout path); zero keeps kSpinLimit.
+__device__ __forceinline__ uint32_t spin_limit(const SyncArea* sync) {
+  const uint32_t v = sync->pad;
+  return v ? v : kSpinLimit;
+}
+
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
@@ -109,7 +116,7 @@ __device__ bool wait_flag(const uint32_t* flag, SyncArea* sync, int32_t* status)
         ok = 0;
         break;
       }
-      if (++spins > kSpinLimit) {
+      if (++spins > spin_limit(sync)) {
         __hip_atomic_store(&sync->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (status) atomicOr(status, 2);
         ok = 0;
@@ -586,7 +593,7 @@ __device__ uint64_t msg_wait(uint64_t* p, SyncArea* sync, int32_t* status) {
   uint64_t m;
   while ((m = msg_get(p)) == kEmpty) {
     if (__hip_atomic_load(&sync->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
-    if (++spins > kSpinLimit) {
+    if (++spins > spin_limit(sync)) {
       __hip_atomic_store(&sync->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (status) atomicOr(status, 2);
       break;
@@ -615,7 +622,7 @@ __device__ bool msg_get16(const uint64_t* p, F off, double (&v)[16], SyncArea* s
     if (all) return true;
     if (__hip_atomic_load(&sync->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
       return false;
-    if (++spins > kSpinLimit) {
+    if (++spins > spin_limit(sync)) {
       __hip_atomic_store(&sync->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (status) atomicOr(status, 2);
       return false;
@@ -679,7 +686,7 @@ __device__ bool tagged_poll16(const uint64_t* p, uint32_t seq, Mfma<float>::acc_
     if (tagged_take16(m, seq, acc)) return true;
     if (__hip_atomic_load(&sync->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
       return false;
-    if (++spins > kSpinLimit) {
+    if (++spins > spin_limit(sync)) {
       __hip_atomic_store(&sync->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (status) atomicOr(status, 2);
       return false;
@@ -742,7 +749,7 @@ __device__ bool tagged_get16(const uint64_t* t, uint32_t seq, F elem, float (&v)
     if (all) return true;
     if (__hip_atomic_load(&sync->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
       return false;
-    if (++spins > kSpinLimit) {
+    if (++spins > spin_limit(sync)) {
       __hip_atomic_store(&sync->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (status) atomicOr(status, 2);
       return false;
@@ -1438,7 +1445,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
           if (tid == 0) {
             if (__hip_atomic_load(&sync->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
               live = false;
-            } else if (++spins > kSpinLimit) {
+            } else if (++spins > spin_limit(sync)) {
               __hip_atomic_store(&sync->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
               if (status) atomicOr(status, 2);
               live = false;

@@ -35,7 +35,7 @@ EXPORTS = ("ddc_default_lm_opts", "ddc_create", "ddc_destroy", "ddc_set_stream",
            "ddc_workspace_bytes", "ddc_predict", "ddc_predict_factored", "ddc_residual",
            "ddc_residual_noalloc", "ddc_add_model",
            "ddc_build_normal_eq", "ddc_damped_solve", "ddc_lm_solve", "ddc_calibrate",
-           "ddc_cost_gradient", "ddc_enable_timing", "ddc_enable_timers", "ddc_get_timing", "ddc_calibrate_footprint",
+           "ddc_cost_gradient", "ddc_set_wait_limit", "ddc_enable_timing", "ddc_enable_timers", "ddc_get_timing", "ddc_calibrate_footprint",
            "ddc_server_create", "ddc_server_destroy", "ddc_server_submit", "ddc_server_wait",
            "ddc_server_stats", "ddc_server_last_error")
 
@@ -109,6 +109,7 @@ _lib.ddc_calibrate.argtypes = [_vp, ct.POINTER(Obs), ct.POINTER(Sky), _vp, _vp, 
                                _vp, ct.POINTER(LMInfo), ct.POINTER(LMStep)]
 _lib.ddc_cost_gradient.argtypes = [_vp, ct.POINTER(Obs), ct.c_int32, _vp, _vp, _vp, ct.c_int32, _vp,
                                    ct.POINTER(ct.c_double)]
+_lib.ddc_set_wait_limit.argtypes = [_vp, ct.c_uint32]
 _lib.ddc_enable_timing.argtypes = [_vp, ct.c_int32]
 _lib.ddc_enable_timers.argtypes = [_vp, ct.c_uint32]
 _lib.ddc_get_timing.argtypes = [_vp, ct.c_int32, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_double),
@@ -304,6 +305,10 @@ class Context:
         self._check(_lib.ddc_cost_gradient(self.h, ct.byref(obs.c), K, _ptr(vis), _ptr(coh), _ptr(jones),
                                            precision, _ptr(grad), ct.byref(cost) if want_cost else None))
         return (cost.value if want_cost else None), grad
+
+    def set_wait_limit(self, polls: int):
+        """ddc_set_wait_limit: bound every inter-workgroup wait at `polls` polls (0: default)."""
+        self._check(_lib.ddc_set_wait_limit(self.h, int(polls)))
 
     def enable_timing(self, on=True, timers=None):
         """Time every kernel class (on), none, or only those listed in timers (TIMER_*)."""

@@ -13,6 +13,9 @@ failure paths, through the C ABI.
   a rejection counted as a failed factorisation, on both sides, in both precisions.
 * NaN in the data makes the cost non-finite: DDC_ENONFINITE from ddc_lm_solve (the Jones
   untouched), ddc_calibrate and ddc_residual.
+* With the inter-workgroup waits bounded at one retry (ddc_set_wait_limit), the solves time
+  out and the calls report DDC_ETIMEOUT with the Jones untouched; the context then solves
+  normally.  Every kernel still leaves normally: the bound only makes waits give up sooner.
 """
 import math
 
@@ -173,3 +176,38 @@ def test_nonfinite_data_is_reported(dd, ctx):
         J = J0.clone()
         info = ctx.lm_solve(d["obs"], d["V"], coh[0].contiguous(), J[0], dd.default_lm_opts(n_iter=2, precision=prec))
         assert info.n_accept >= 1
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
+def test_wait_timeout_is_reported_and_the_context_recovers(dd, n64, prec):
+    # With every inter-workgroup wait bounded at one retry, the factorisation and the solves
+    # give up on the first tile or block that is not ready at once: they abort (every
+    # workgroup leaves), the step is rejected, and the call reports DDC_ETIMEOUT without an
+    # info struct, with the Jones untouched.  The same context then solves normally.
+    import torch
+    ob, V, C, J0, Jo, io = n64
+    ctx = dd.Context(0)
+    try:
+        d = to_dev(dd, ob, prec, V=V)
+        coh = ctx.predict(d["obs"], d["sky"], prec)[0].contiguous()
+        J = torch.as_tensor(dd.jones_real(J0), device="cuda").contiguous()
+        J_start = J.clone()
+        ctx.set_wait_limit(1)
+        with pytest.raises(dd.DdcError) as e:
+            ctx.lm_solve(d["obs"], d["V"], coh, J, dd.default_lm_opts(n_iter=3, precision=prec),
+                         want_info=False)
+        assert e.value.status == dd.ETIMEOUT
+        assert torch.equal(J, J_start)
+        n = 8 * ob.N
+        H = torch.eye(n, dtype=torch.float64 if prec == 0 else torch.float32, device="cuda") * 4.0
+        g = torch.ones(n, dtype=H.dtype, device="cuda")
+        with pytest.raises(dd.DdcError) as e:
+            ctx.damped_solve(H, g, 0.0, prec)
+        assert e.value.status == dd.ETIMEOUT
+        ctx.set_wait_limit(0)
+        info = ctx.lm_solve(d["obs"], d["V"], coh, J, dd.default_lm_opts(n_iter=CFG64.n_lm, precision=prec))
+        err = align.align_error(dd.jones_complex(J.cpu().numpy()), Jo)
+        assert err <= (1e-8 if prec == 0 else 1e-4), err
+        assert abs(info.cost - io.cost) <= (1e-9 if prec == 0 else 1e-5) * io.cost
+    finally:
+        ctx.close()

@@ -1347,7 +1347,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
       }
       auto step = [&](auto slot, int q) {
         constexpr int S = decltype(slot)::value;
-        fetch(std::integral_constant<int, (S + PF) % NS>{}, q + PF);
+        // FP64 (two slots): the operands of the next step are fetched here, a whole step ahead
+        if constexpr (NS == 2) fetch(std::integral_constant<int, (S + PF) % NS>{}, q + PF);
         const int I = solve_block<FWD>(T, q);
         double pv = 0.0;
         if (q >= D) {
@@ -1373,10 +1374,19 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
         cacc[D - 2] = 0.0;
         if (wp == 0) s_vec[wr] = sv;
         __syncthreads();
+        if constexpr (NS == 3) {
+          // FP32 (three slots): the next block's partial sum is fetched here, one step ahead,
+          // and then the operands of the step two ahead; the partial-sum load is older than
+          // those tile loads, so the in-order memory-counter wait for it at the next step does
+          // not cover them
+          mq[(S + 1) % NS] = msg_get(psum + 64 * solve_block<FWD>(T, q + 1 < T ? q + 1 : T - 1) + wr);
+          fetch(std::integral_constant<int, (S + PF) % NS>{}, q + PF);
+        }
         double y4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int u = 0; u < 16; ++u) y4[u & 3] = fma((double)inv[S][u], s_vec[wp * 16 + u], y4[u & 3]);
-        mq[(S + 2) % NS] = msg_get(psum + 64 * solve_block<FWD>(T, q + 2 < T ? q + 2 : T - 1) + wr);
+        if constexpr (NS == 2)
+          mq[(S + 2) % NS] = msg_get(psum + 64 * solve_block<FWD>(T, q + 2 < T ? q + 2 : T - 1) + wr);
         const double xi = quad_sum((y4[0] + y4[1]) + (y4[2] + y4[3]));
         if (wp == 0) {
           x[64 * I + wr] = xi;

@@ -16,6 +16,10 @@ Fixtures (one ``.npz`` each, loaded with ``numpy.load`` without pickles):
   clusters x 20 sources, T = 10, F = 4 channels over 140-160 MHz), 5 SAGE sweeps x 10 LM
   iterations in FP64 from identity Jones.  Stores the final Jones of every cluster, the
   per-visit costs and the final total cost.
+* ``sage_n512_k4_seed0``: SAGE at the SKA1-LOW station count with the bench workload's
+  cluster size and schedule (N = 512, 50 sources per cluster, T = 10, 20 km disk,
+  J = I + 0.2 CN(0,1), 3 sweeps x 10 LM iterations) on four clusters, in FP64 from identity
+  Jones.  Stored like the N = 128 run.
 """
 from __future__ import annotations
 
@@ -37,10 +41,14 @@ from paper_1910_13908_amd import synth  # noqa: E402
 LM_N512 = synth.ObsConfig(512, 1, 50, 10, (150e6,), disk_radius_m=20000.0, jones_amp=0.2,
                           n_sweeps=1, n_lm=10)
 SAGE_N128 = synth.CONFIGS["n128_k10"]
+# the SKA1-LOW workload's station count, cluster size and schedule with four of its clusters
+SAGE_N512 = synth.ObsConfig(512, 4, 50, 10, (150e6,), disk_radius_m=20000.0, jones_amp=0.2,
+                            n_sweeps=3, n_lm=10)
 
 FIXTURES = {
     "lm_n512_k1_seed0": (LM_N512, 0),
     "sage_n128_k10_seed0": (SAGE_N128, 0),
+    "sage_n512_k4_seed0": (SAGE_N512, 0),
 }
 
 

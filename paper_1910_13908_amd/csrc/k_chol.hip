@@ -1307,9 +1307,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
       // Chain worker.  Operands of a position (the row parts of X_II and of the D-1 coupling
       // tiles, the right-hand side and the accumulation target) sit in one of NS register
       // slots, filled PF = NS-1 steps ahead at the start of a step, so a tile fetch has PF
-      // whole steps to arrive.  The partial-sum message of a position is fetched two steps
-      // ahead, after that step's tile fetches, so it is the youngest load in flight when it
-      // is needed (the vector-memory counter is in order).  Fetches are unconditional with
+      // whole steps to arrive.  In FP32 the partial-sum message of the next position is
+      // fetched in the middle of a step, one step ahead (two ahead it was usually not yet
+      // published and the step polled for it), and before the tile loads issued there, so
+      // its wait covers none of them (the vector-memory counter is in order); FP64 keeps it
+      // two steps ahead.  Fetches are unconditional with
       // positions clamped into range (values fetched for a position that does not exist are
       // never used): a conditional load would make the wave wait for it at the join.  The
       // step loop is unrolled by NS, so every slot is a fixed set of registers.
@@ -1385,6 +1387,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
         double y4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int u = 0; u < 16; ++u) y4[u & 3] = fma((double)inv[S][u], s_vec[wp * 16 + u], y4[u & 3]);
+        // FP64: the partial sum two steps ahead (one step ahead measured 1 % slower here)
         if constexpr (NS == 2)
           mq[(S + 2) % NS] = msg_get(psum + 64 * solve_block<FWD>(T, q + 2 < T ? q + 2 : T - 1) + wr);
         const double xi = quad_sum((y4[0] + y4[1]) + (y4[2] + y4[3]));

@@ -16,6 +16,8 @@ which calls only the FP64 oracle and the seeded input generator).
   T = 10, F = 4, 5 SAGE sweeps x 10 LM): the stored oracle calibration against the GPU
   path in both precisions, per cluster after alignment and per visit.
 * The FP32 factorisation reports a non-positive pivot (DDC_ENOTPD), as the FP64 one does.
+* SAGE at N = 512 with the bench workload's cluster size and schedule (50 sources per
+  cluster, 3 sweeps x 10 LM) on four clusters, against the stored oracle calibration.
 """
 import os
 
@@ -208,4 +210,46 @@ def test_sage_n128_k10_against_stored_oracle(dd, ctx, n128, prec):
     # an accept/reject decided at the rounding level of the cost sums moves one side a step
     # ahead on that visit (the next visits of the cluster absorb it, as the final results
     # above show), so visits are held to the size of such a step, 1e-7, in FP64
+    assert vrel.max() <= (1e-7 if prec == dd.FP64 else tol_c), vrel.max()
+
+
+SAGE_N512 = synth.ObsConfig(512, 4, 50, 10, (150e6,), disk_radius_m=20000.0, jones_amp=0.2,
+                            n_sweeps=3, n_lm=10)
+
+
+@pytest.fixture(scope="module")
+def n512_sage():
+    print("\n[n512 sage] oracle predict of 4 clusters x 50 sources over 1308160 visibilities", flush=True)
+    ob = synth.make_obs(SAGE_N512, seed=0)
+    V, C = rime.make_vis(ob)
+    del C
+    return ob, V, _fixture("sage_n512_k4_seed0")
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
+def test_sage_n512_k4_against_stored_oracle(dd, ctx, n512_sage, prec):
+    # the whole path at the SKA1-LOW station count: predict, 3 SAGE sweeps x 10 LM iterations
+    # of 4 clusters (the bench workload's cluster size and schedule), against the stored
+    # FP64 oracle calibration; bars as for the N = 128 workload
+    import torch
+    ob, V, fx = n512_sage
+    cfg = SAGE_N512
+    obs, sky = dd.device_obs(ob), dd.device_sky(ob)
+    dt = torch.float64 if prec == dd.FP64 else torch.float32
+    Vd = torch.as_tensor(dd.planes(V), dtype=dt, device="cuda").contiguous()
+    Jd = torch.as_tensor(dd.jones_real(synth.identity_jones(ob.K, ob.N)), device="cuda").contiguous()
+    R = torch.empty_like(Vd)
+    infos = ctx.calibrate(obs, sky, Vd, Jd, cfg.n_sweeps,
+                          dd.default_lm_opts(n_iter=cfg.n_lm, precision=prec), res=R)
+    Jg = dd.jones_complex(Jd.cpu().numpy())
+    errs = [align.align_error(Jg[k], fx["jones"][k]) for k in range(ob.K)]
+    final = float(np.sum(R.double().cpu().numpy() ** 2))
+    ref = float(fx["final_cost"])
+    visit = np.array([[i.cost for i in row] for row in infos])
+    vrel = np.abs(visit - fx["visit_cost"]) / fx["visit_cost"]
+    print(f"[n512 sage {'fp64' if prec == 0 else 'mixed'}] max gain error {max(errs):.2e}, final "
+          f"cost {final:.9f} vs {ref:.9f}, per-visit cost error max {vrel.max():.2e}", flush=True)
+    tol_j, tol_c = (1e-8, 1e-9) if prec == dd.FP64 else (1e-4, 1e-5)
+    assert max(errs) <= tol_j, errs
+    assert abs(final - ref) <= tol_c * ref
     assert vrel.max() <= (1e-7 if prec == dd.FP64 else tol_c), vrel.max()

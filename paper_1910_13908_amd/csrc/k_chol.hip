@@ -696,39 +696,41 @@ __device__ bool tagged_poll16(const uint64_t* p, uint32_t seq, Mfma<float>::acc_
 }
 
 // In FP32 every tile a task hands to another (L_IJ, and in the slot of the diagonal tile
-// (s, s) the inverse X_s) is also written as a tagged copy in natural row-major order, slot e =
-// element e, and read from there, so no task publishes a flag or runs a fence.  The copies sit
-// after the look-ahead tiles' messages, tile t at t * 4096 (column-major tile order).
+// (s, s) the inverse X_s) is also written as a tagged copy and read from there, so no task
+// publishes a flag or runs a fence.  The copy is laid out in the order its readers load it:
+// a reader's thread t holds elements 4 (t + 256 i) + u (i, u = 0..3; the tile_fetch layout),
+// and element e = 4 (t + 256 i) + u sits in slot (4 i + u) * 256 + t, so that every load
+// instruction of a wave reads 512 contiguous bytes.  The copies sit after the look-ahead
+// tiles' messages, tile t at t * 4096 (column-major tile order).
 __device__ __forceinline__ uint64_t* tile_slots(void* base, int T, uint32_t ti) {
   return reinterpret_cast<uint64_t*>(base) + (int64_t)T * 2 * 16 * kThreads + (int64_t)ti * 4096;
+}
+__device__ __forceinline__ int slot_of(int e) {
+  return ((e >> 10) * 4 + (e & 3)) * kThreads + ((e >> 2) & (kThreads - 1));
+}
+__device__ __forceinline__ int elem_of_slot(int q) {
+  return 4 * ((q & (kThreads - 1)) + kThreads * (q >> 10)) + ((q >> 8) & 3);
 }
 // FP32: the forward-substitution blocks y_K as messages (T x 64 slots, kEmpty between launches)
 __device__ __forceinline__ uint64_t* y_slots(void* base, int T) {
   return reinterpret_cast<uint64_t*>(base) + (int64_t)T * 2 * 16 * kThreads +
          (int64_t)T * (T + 1) / 2 * 4096;
 }
-// The 16 elements of thread tid in the MFMA accumulator layout (acc_to_global) as tagged slots.
-__device__ __forceinline__ void tagged_put_acc(uint64_t* t, uint32_t seq,
-                                               const Mfma<float>::acc_t (&acc)[2][2], int qr,
-                                               int qc);
 __device__ __forceinline__ void tagged_put(uint64_t* p, uint32_t seq, float v) {
   __hip_atomic_store(p, ((uint64_t)seq << 32) | (uint64_t)__float_as_uint(v), __ATOMIC_RELAXED,
                      __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void tagged_put_acc(uint64_t* t, uint32_t seq,
-                                               const Mfma<float>::acc_t (&acc)[2][2], int qr,
-                                               int qc) {
-  const int lane = threadIdx.x & 63;
+// The tagged copy of a 64x64 LDS tile (row stride STR): thread t stores slots k * 256 + t,
+// k = 0..15, so each store instruction of a wave writes 512 contiguous bytes; slot 4095 (the
+// one waiting tasks watch) is the last store of the last wave.
+__device__ __forceinline__ void tagged_put_lds(uint64_t* t, uint32_t seq, const float* X) {
+  constexpr int STR = Mfma<float>::STR;
 #pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = qr * 32 + bi * 16 + out_row<float>(lane, v);
-        const int c = qc * 32 + bj * 16 + out_col(lane, v);
-        tagged_put(t + r * 64 + c, seq, acc[bi][bj][v]);
-      }
+  for (int k = 0; k < 16; ++k) {
+    const int q = k * kThreads + threadIdx.x;
+    const int e = elem_of_slot(q);
+    tagged_put(t + q, seq, X[(e >> 6) * STR + (e & 63)]);
+  }
 }
 // v[j] = element base_e[j] of a tagged tile once all 16 carry tag seq (bounded poll).
 template <typename F>
@@ -763,11 +765,75 @@ __device__ __forceinline__ bool tagged_tile_fetch(const uint64_t* t, uint32_t se
                                                   int32_t* status) {
   float v[16];
   const int tid = threadIdx.x;
-  const bool ok = tagged_get16(t, seq, [&](int j) { return 4 * (tid + kThreads * (j >> 2)) + (j & 3); },
-                               v, sync, status);
+  const bool ok = tagged_get16(t, seq, [&](int j) { return j * kThreads + tid; }, v, sync, status);
 #pragma unroll
   for (int i = 0; i < 4; ++i) r.v[i] = f32x4{v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]};
   return ok;
+}
+
+// The same tile as tagged_tile_fetch in two halves: tagged_tile_issue starts the 16 loads and
+// tagged_tile_take converts them once every tag matches (false if one does not yet), so the
+// loads can stay in flight over other work.
+__device__ __forceinline__ void tagged_tile_issue(const uint64_t* t, uint64_t (&m)[16]) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < 16; ++j)
+    m[j] = __hip_atomic_load(t + j * kThreads + tid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ bool tagged_tile_take(const uint64_t (&m)[16], uint32_t seq,
+                                                 TileRegs<float>& r) {
+  bool all = true;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) all &= (uint32_t)(m[j] >> 32) == seq;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    r.v[i] = f32x4{__uint_as_float((uint32_t)m[4 * i]), __uint_as_float((uint32_t)m[4 * i + 1]),
+                   __uint_as_float((uint32_t)m[4 * i + 2]), __uint_as_float((uint32_t)m[4 * i + 3])};
+  return all;
+}
+
+// Bounded wait until the last slot a tagged tile's writer stores (element 4095: the last
+// store of its last wave) carries tag seq.  Every lane reads the same slot, so a poll is one
+// request per wave; the whole tile is fetched (and every tag checked) only after it.  With
+// dozens of tasks waiting on one tile, whole-tile polls would load the lines its writer is
+// still storing to many times over.
+__device__ bool tagged_watch(const uint64_t* t, uint32_t seq, SyncArea* sync, int32_t* status) {
+  uint32_t spins = 0;
+  while ((uint32_t)(__hip_atomic_load(t + 4095, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> 32) != seq) {
+    if (__hip_atomic_load(&sync->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
+      return false;
+    if (++spins > spin_limit(sync)) {
+      __hip_atomic_store(&sync->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (status) atomicOr(status, 2);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+  return true;
+}
+
+// Both tiles of an accumulation step, polled together (bounded): one round trip per poll
+// for the pair instead of one per tile.
+__device__ bool tagged_tile_fetch2(const uint64_t* ta, const uint64_t* tb, uint32_t seq,
+                                   TileRegs<float>& ra, TileRegs<float>& rb, SyncArea* sync,
+                                   int32_t* status) {
+  uint32_t spins = 0;
+  for (;;) {
+    uint64_t ma[16], mb[16];
+    tagged_tile_issue(ta, ma);
+    tagged_tile_issue(tb, mb);
+    const bool ga = tagged_tile_take(ma, seq, ra);
+    const bool gb = tagged_tile_take(mb, seq, rb);
+    if (ga && gb) return true;
+    if (__hip_atomic_load(&sync->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
+      return false;
+    if (++spins > spin_limit(sync)) {
+      __hip_atomic_store(&sync->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (status) atomicOr(status, 2);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
 }
 
 // Roles of the factorisation.  Ticket 0 makes its workgroup the diagonal worker (DW): it
@@ -858,13 +924,33 @@ __device__ __forceinline__ bool accumulate(typename Mfma<R>::acc_t (&acc1)[2][2]
   int buf = 0;
   for (int K = 0; K < nK; ++K) {
     const bool more = K + 1 < nK;
-    if (more && (TAG || ok)) {
+    // FP32: the next pair's loads are issued before this pair's products and taken after
+    // them, so a pair that is still being written is waited for behind the products
+    uint64_t ma[16], mb[16];
+    if constexpr (TAG) {
+      const int Kn = more ? K + 1 : K;
+      tagged_tile_issue(tile_slots(tagbase, T, tile_index(IA, Kn, T)), ma);
+      tagged_tile_issue(tile_slots(tagbase, T, tile_index(IB, Kn, T)), mb);
+    } else if (more && ok) {
       wait_k(K + 1);
       fetch_k(K + 1);
     }
     const R* As = lds + buf * 2 * TILE;
     tile_mma<R, true>(acc1, As, As + TILE, qr, qc);
     if constexpr (TWO) tile_mma<R, true>(acc2, As, As, qr, qc);
+    if constexpr (TAG) {
+      if (more) {
+        const bool ga = tagged_tile_take(ma, seq, ra);
+        const bool gb = tagged_tile_take(mb, seq, rb);
+        if (!(ga && gb)) {
+          const uint64_t* ta = tile_slots(tagbase, T, tile_index(IA, K + 1, T));
+          const uint64_t* tb = tile_slots(tagbase, T, tile_index(IB, K + 1, T));
+          bool w = ga || tagged_watch(ta, seq, sync, status);
+          w = (gb || tagged_watch(tb, seq, sync, status)) && w;
+          ok = w && tagged_tile_fetch2(ta, tb, seq, ra, rb, sync, status) && ok;
+        }
+      }
+    }
     if (more) {
       R* nxt = lds + (buf ^ 1) * 2 * TILE;
       tile_stash<R>(ra, nxt);
@@ -962,12 +1048,15 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
 #pragma unroll
             for (int bj = 0; bj < 2; ++bj) ls[bi][bj] = acc_t{0, 0, 0, 0};
           tile_mma<R, false>(ls, Abuf, Xprev, qr, qc);      // L_{s,s-1} = A X_{s-1}^T
-          acc_to_global<R>(ls, Lt + (int64_t)tile_index(st, st - 1, T) * 4096, qr, qc);
-          acc_to_lds<R>(ls, Lbuf, qr, qc);
+          // FP32: the tagged copy, which the waiting tasks read, is stored before the plain one
           if constexpr (sizeof(R) == 4) {
-            tagged_put_acc(tile_slots(part_raw, T, tile_index(st, st - 1, T)), seq, ls, qr, qc);
+            acc_to_lds<R>(ls, Lbuf, qr, qc);
             __syncthreads();
+            tagged_put_lds(tile_slots(part_raw, T, tile_index(st, st - 1, T)), seq, Lbuf);
+            acc_to_global<R>(ls, Lt + (int64_t)tile_index(st, st - 1, T) * 4096, qr, qc);
           } else {
+            acc_to_global<R>(ls, Lt + (int64_t)tile_index(st, st - 1, T) * 4096, qr, qc);
+            acc_to_lds<R>(ls, Lbuf, qr, qc);
             publish(flags + tile_index(st, st - 1, T));
           }
           __syncthreads();
@@ -1001,11 +1090,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
         if (bad && tid == 0 && status) atomicOr(status, 1);
         R* dstX = Linv + (int64_t)st * 4096;
         if constexpr (sizeof(R) == 4) {
-          uint64_t* tx = tile_slots(part_raw, T, tile_index(st, st, T));
-          for (int e = tid; e < 4096; e += kThreads) {
-            const R xv = Xcur[(e >> 6) * STR + (e & 63)];
-            dstX[e] = xv;
-            tagged_put(tx + e, seq, xv);
+          // the tagged copy first (slot 4095, which waiting tasks watch, is among the last
+          // stores), then the plain one
+          tagged_put_lds(tile_slots(part_raw, T, tile_index(st, st, T)), seq, Xcur);
+#pragma unroll
+          for (int k = 0; k < 16; ++k) {
+            const int e = tid + kThreads * k;
+            dstX[e] = Xcur[(e >> 6) * STR + (e & 63)];
           }
           __syncthreads();
         } else {
@@ -1028,13 +1119,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
       for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj) accp[bi][bj] = acc_t{0, 0, 0, 0};
+      // the H tile (with the damping on the diagonal) is loaded before the products and added
+      // after them, off the worker's path; the sum rounds as the worker's own
+      // (H + mu I) + partial
+      acc_t hp[2][2];
+      acc_load_h<R>(hp, Hc, ld, s, which ? s : s - 1, which ? mu : 0.0, qr, qc);
       ok = accumulate<R, false>(accp, dummy, Lt, T, s, which ? s : s - 1, s - 1, lds, sync, flags,
                                 status, qr, qc, part_raw, seq);
       {
-        // the H tile (with the damping on the diagonal) is added here, after the products
-        // and off the worker's path; the sum rounds as the worker's own (H + mu I) + partial
-        acc_t hp[2][2];
-        acc_load_h<R>(hp, Hc, ld, s, which ? s : s - 1, which ? mu : 0.0, qr, qc);
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -1064,8 +1156,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
       acc_to_lds<R>(acc, lds, qr, qc);
       if constexpr (sizeof(R) == 4) {
         TileRegs<R> xr;
-        const bool g = tagged_tile_fetch(tile_slots(part_raw, T, tile_index(J, J, T)), seq, xr,
-                                         sync, status);
+        const uint64_t* tx = tile_slots(part_raw, T, tile_index(J, J, T));
+        const bool g = tagged_watch(tx, seq, sync, status) &&
+                       tagged_tile_fetch(tx, seq, xr, sync, status);
         ok = __syncthreads_and(ok && g) != 0;
         tile_stash<R>(xr, lds + TILE);
       } else {
@@ -1079,11 +1172,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj) out[bi][bj] = acc_t{0, 0, 0, 0};
       tile_mma<R, false>(out, lds, lds + TILE, qr, qc);
-      acc_to_global<R>(out, Lt + (int64_t)tile_index(I, J, T) * 4096, qr, qc);
       if constexpr (sizeof(R) == 4) {
-        tagged_put_acc(tile_slots(part_raw, T, tile_index(I, J, T)), seq, out, qr, qc);
+        acc_to_lds<R>(out, lds + 2 * TILE, qr, qc);      // tile 2 is free after the accumulation
+        __syncthreads();
+        tagged_put_lds(tile_slots(part_raw, T, tile_index(I, J, T)), seq, lds + 2 * TILE);
+        acc_to_global<R>(out, Lt + (int64_t)tile_index(I, J, T) * 4096, qr, qc);
         __syncthreads();
       } else {
+        acc_to_global<R>(out, Lt + (int64_t)tile_index(I, J, T) * 4096, qr, qc);
         publish(flags + tile_index(I, J, T));
       }
       __syncthreads();
@@ -1101,13 +1197,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
           float lv[16];
           double yk[16];
           g = tagged_get16(tile_slots(part_raw, T, tile_index(J, K, T)), seq,
-                           [&](int c) { return r * 64 + pt * 16 + c; }, lv, sync, status) && g;
+                           [&](int c) { return slot_of(r * 64 + pt * 16 + c); }, lv, sync, status) && g;
           g = msg_get16(ymsg + 64 * K + pt * 16, [](int c) { return c; }, yk, sync, status) && g;
 #pragma unroll
           for (int c = 0; c < 16; ++c) acc = fma((double)lv[c], yk[c], acc);
         }
         g = tagged_get16(tile_slots(part_raw, T, tile_index(J, J, T)), seq,
-                         [&](int c) { return r * 64 + pt * 16 + c; }, iv, sync, status) && g;
+                         [&](int c) { return slot_of(r * 64 + pt * 16 + c); }, iv, sync, status) && g;
         ok = __syncthreads_and(g) != 0;
       } else {
         for (int K = 0; K < J && ok; ++K) {

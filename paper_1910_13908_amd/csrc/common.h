@@ -172,9 +172,10 @@ hipError_t launch_cholesky(const R* Hc, int ld, int n_pad, const double* mu_dev,
                            int32_t* status, hipStream_t st, int n_wg);
 // dst tile t = transpose of src tile t for ntiles packed 64x64 tiles, and likewise dst2/src2
 // for ntiles2 tiles, in one launch (the backward solve reads the transposed factor and
-// inverses); skipped when lm reports a failed factorisation.
+// inverses); both the transposed copies and, in place, the source tiles are left in the
+// solves' tile layout; skipped when lm reports a failed factorisation.
 template <typename R>
-hipError_t launch_transpose_tiles(const R* src, R* dst, int ntiles, const R* src2, R* dst2,
+hipError_t launch_transpose_tiles(R* src, R* dst, int ntiles, R* src2, R* dst2,
                                   int ntiles2, const LMState* lm, hipStream_t st);
 // x = L^{-1} b (forward: Lt, Linv) or L^{-T} b (backward: pass the transposed copies LtT,
 // LinvT); acc_out (nullable) += x.  psum and xpub: 64 T

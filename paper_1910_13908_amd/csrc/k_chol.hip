@@ -1002,23 +1002,21 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
       R* Lbuf = lds + 3 * TILE;
       zero_upper_blocks<R>(Xprev);
       zero_upper_blocks<R>(Xcur);
+      uint64_t mda[16], mdd[16];
+      if constexpr (sizeof(R) == 4) tagged_issue16(tagged_slots(part_raw, 0, 0), mda);
       for (int st = 0; st < T; ++st) {
         // Steps 0 and 1 start from H; later steps from the two look-ahead tiles (H already
-        // added).  The H loads come first and, in FP32, both tiles' loads are issued on every
-        // step (the slots of steps 0 and 1 exist and go unused), so that on every path these 32
-        // loads are the youngest in flight: the in-order memory-counter waits then leave the
-        // diagonal tile's 16 loads in flight over the subdiagonal product and the diagonal
-        // update, which need only the subdiagonal tile.
+        // added).  In FP32 the subdiagonal tile's loads were issued before the previous step's
+        // stores; the diagonal tile's 16 loads are issued here on every step (the slots of
+        // steps 0 and 1 exist and go unused), after any H loads, so that the in-order
+        // memory-counter waits leave them in flight over the subdiagonal product and the
+        // diagonal update, which need only the subdiagonal tile.
         acc_t accd[2][2], accs[2][2];
         if (st < 2) {
           acc_load_h<R>(accd, Hc, ld, st, st, mu, qr, qc);
           if (st == 1) acc_load_h<R>(accs, Hc, ld, st, st - 1, 0.0, qr, qc);
         }
-        uint64_t mda[16], mdd[16];
-        if constexpr (sizeof(R) == 4) {
-          tagged_issue16(tagged_slots(part_raw, st, 0), mda);
-          tagged_issue16(tagged_slots(part_raw, st, 1), mdd);
-        }
+        if constexpr (sizeof(R) == 4) tagged_issue16(tagged_slots(part_raw, st, 1), mdd);
         if (st >= 1) {
           if (st >= 2) {
             if constexpr (sizeof(R) == 4) {
@@ -1090,13 +1088,18 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
         if (bad && tid == 0 && status) atomicOr(status, 1);
         R* dstX = Linv + (int64_t)st * 4096;
         if constexpr (sizeof(R) == 4) {
-          // the tagged copy first (slot 4095, which waiting tasks watch, is among the last
-          // stores), then the plain one
+          // The next step's subdiagonal look-ahead tile is normally published by now: its
+          // loads go out before this step's stores, so the wait for them at the next step
+          // does not cover the stores (the vector-memory counter is in order).  Then the
+          // tagged copy of the inverse (slot 4095, which waiting tasks watch, is among the
+          // last stores) and the plain one.
+          tagged_issue16(tagged_slots(part_raw, st + 1 < T ? st + 1 : T - 1, 0), mda);
           tagged_put_lds(tile_slots(part_raw, T, tile_index(st, st, T)), seq, Xcur);
 #pragma unroll
-          for (int k = 0; k < 16; ++k) {
-            const int e = tid + kThreads * k;
-            dstX[e] = Xcur[(e >> 6) * STR + (e & 63)];
+          for (int k = 0; k < 4; ++k) {
+            const int e4 = 4 * (tid + kThreads * k);
+            *reinterpret_cast<f32x4*>(dstX + e4) =
+                *reinterpret_cast<const f32x4*>(Xcur + (e4 >> 6) * STR + (e4 & 63));
           }
           __syncthreads();
         } else {
@@ -1315,24 +1318,29 @@ __device__ __forceinline__ double quad_sum(double v) {
 template <bool FWD>
 __device__ __forceinline__ int solve_block(int T, int q) { return FWD ? q : T - 1 - q; }
 
-// The thread's 16 operands of a tile row: 16 contiguous elements, fetched as 16-byte vectors.
+// Solve layout of the tiles the solves read (k_transpose_tiles writes it, for the factor and
+// inverse tiles in place and for their transposed copies): the 16-byte chunk j of (row r,
+// columns 16 p ..) sits at chunk j * 256 + tl(r, p), with tl(r, p) = 64 (r / 16) + 4 (r % 16)
+// + p the thread of the solve's chain worker that reads it, so that each load instruction of
+// the worker's waves reads 1 KB of contiguous memory.
+__device__ __forceinline__ int solve_tl(int r, int p) { return 64 * (r >> 4) + 4 * (r & 15) + p; }
 template <typename R>
-__device__ __forceinline__ void load16(const R* __restrict__ p, R (&v)[16]) {
+__device__ __forceinline__ void load16_solve(const R* __restrict__ tile, int r, int p, R (&v)[16]) {
+  constexpr int V = 16 / (int)sizeof(R);
+  const int tl = solve_tl(r, p);
   if constexpr (sizeof(R) == 4) {
-    const f32x4* p4 = reinterpret_cast<const f32x4*>(p);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const f32x4 t = p4[j];
+      const f32x4 t = *reinterpret_cast<const f32x4*>(tile + (j * kThreads + tl) * V);
       v[4 * j] = t[0];
       v[4 * j + 1] = t[1];
       v[4 * j + 2] = t[2];
       v[4 * j + 3] = t[3];
     }
   } else {
-    const f64x2* p2 = reinterpret_cast<const f64x2*>(p);
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const f64x2 t = p2[j];
+      const f64x2 t = *reinterpret_cast<const f64x2*>(tile + (j * kThreads + tl) * V);
       v[2 * j] = t[0];
       v[2 * j + 1] = t[1];
     }
@@ -1341,12 +1349,12 @@ __device__ __forceinline__ void load16(const R* __restrict__ p, R (&v)[16]) {
 
 // Tile coupling block I to block K (K before I in solve order), row r, columns 16 part ..:
 // forward, row r of L_IK from the factor; backward, column r of L_KI, which is row r of the
-// transposed tile, from the transposed copy (L is then the transposed factor).
+// transposed tile, from the transposed copy (L is then the transposed factor); both in the
+// solve layout.
 template <typename R, bool FWD>
 __device__ __forceinline__ void load_coupling(const R* __restrict__ L, int T, int I, int K,
                                               int rc, int part, R (&v)[16]) {
-  const int ti = FWD ? tile_index(I, K, T) : tile_index(K, I, T);
-  load16<R>(L + (int64_t)ti * 4096 + rc * 64 + part * 16, v);
+  load16_solve<R>(L + (int64_t)(FWD ? tile_index(I, K, T) : tile_index(K, I, T)) * 4096, rc, part, v);
 }
 
 // Row r, columns 16 part .. of X_II (forward) or of X_II^T (backward; Linv is then the
@@ -1354,7 +1362,7 @@ __device__ __forceinline__ void load_coupling(const R* __restrict__ L, int T, in
 template <typename R>
 __device__ __forceinline__ void load_inverse(const R* __restrict__ Linv, int I, int rc, int part,
                                              R (&v)[16]) {
-  load16<R>(Linv + (int64_t)I * 4096 + rc * 64 + part * 16, v);
+  load16_solve<R>(Linv + (int64_t)I * 4096, rc, part, v);
 }
 
 // Leave the solve: the last workgroup out restores kEmpty in the message arrays and clears
@@ -1724,12 +1732,12 @@ size_t chol_smem_bytes() {
 }
 
 // Transpose every 64x64 tile of a packed array (ntiles tiles), one workgroup per tile through
-// LDS so that both the reads and the writes are coalesced.  Skipped after a failed
-// factorisation.
+// LDS so that both the reads and the writes are coalesced, and rewrite the source tile in
+// place in the solve layout.  Skipped after a failed factorisation.
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_transpose_tiles(const R* __restrict__ src,
+__global__ __launch_bounds__(kThreads) void k_transpose_tiles(R* __restrict__ src,
                                                               R* __restrict__ dst, int n1,
-                                                              const R* __restrict__ src2,
+                                                              R* __restrict__ src2,
                                                               R* __restrict__ dst2,
                                                               const LMState* __restrict__ lm) {
   __shared__ R t[64][65];
@@ -1737,7 +1745,7 @@ __global__ __launch_bounds__(kThreads) void k_transpose_tiles(const R* __restric
   // blocks [0, n1) transpose tiles of the first array, the rest those of the second
   const bool first = (int)blockIdx.x < n1;
   const int64_t k = first ? blockIdx.x : blockIdx.x - n1;
-  const R* s = (first ? src : src2) + k * 4096;
+  R* s = (first ? src : src2) + k * 4096;
   R* d = (first ? dst : dst2) + k * 4096;
   // all 16 loads of a thread are issued before the first LDS write (a loop that waited for
   // each load in turn ran the kernel at half the rate)
@@ -1750,15 +1758,22 @@ __global__ __launch_bounds__(kThreads) void k_transpose_tiles(const R* __restric
     t[e >> 6][e & 63] = v[q];
   }
   __syncthreads();
+  // the destination in the solve layout (the backward solve's only operands), stored in
+  // order: position pos holds element w of chunk pos / V
+  constexpr int V = 16 / (int)sizeof(R);
 #pragma unroll
   for (int q = 0; q < 4096 / kThreads; ++q) {
-    const int e = threadIdx.x + q * kThreads;
-    d[e] = t[e & 63][e >> 6];
+    const int pos = threadIdx.x + q * kThreads;
+    const int chunk = pos / V, w = pos % V;
+    const int j = chunk >> 8, tl = chunk & 255;
+    const int r = 16 * (tl >> 6) + ((tl & 63) >> 2), c = 16 * (tl & 3) + V * j + w;
+    d[pos] = t[c][r];
+    s[pos] = t[r][c];      // in place: every load of the tile is done (barrier above)
   }
 }
 
 template <typename R>
-hipError_t launch_transpose_tiles(const R* src, R* dst, int ntiles, const R* src2, R* dst2,
+hipError_t launch_transpose_tiles(R* src, R* dst, int ntiles, R* src2, R* dst2,
                                   int ntiles2, const LMState* lm, hipStream_t st) {
   if (ntiles + ntiles2 <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_transpose_tiles<R>, dim3(ntiles + ntiles2), dim3(kThreads), 0, st, src,
@@ -1839,7 +1854,7 @@ hipError_t set_chol_smem_attr() {
                                          const double*, double*, R*, R*, void*, uint32_t,      \
                                          SyncArea*, uint32_t*, uint32_t*, int32_t*,            \
                                          hipStream_t, int);                                    \
-  template hipError_t launch_transpose_tiles<R>(const R*, R*, int, const R*, R*, int,           \
+  template hipError_t launch_transpose_tiles<R>(R*, R*, int, R*, R*, int,          \
                                                 const LMState*, hipStream_t);                  \
   template hipError_t launch_trsv<R>(bool, const R*, const R*, int, const double*, double*,    \
                                      double*, uint64_t*, uint64_t*, SyncArea*, int32_t*,       \

@@ -326,13 +326,14 @@ __device__ __forceinline__ void wave_sync_lds() {
 
 // Wave 0: factor columns 16P..16P+15 (rows >= 16P) in place; returns nonzero on a bad pivot.
 // Lane i keeps its panel row in registers.  Right-looking inside the panel: once column j is
-// scaled, each later column jj takes its rank-1 update with the multiplier L[16P+jj][j],
-// broadcast from lane 16P+jj by readlane; the broadcasts of one column are independent, so
-// only the pivot broadcast, the rsq and one update sit on the serial chain.  The pivot lane
-// holds d itself, so scaling every lane by rsq(d) leaves sqrt(d) on the diagonal.  The whole
-// panel is written back: entries above the diagonal of the tile are never read.
+// scaled, each later column jj takes its rank-1 update with the multiplier L[16P+jj][j] of
+// lane 16P+jj: the next column's by readlane, so that only the pivot broadcast, the rsq and
+// one update sit on the serial chain, the others read back from LDS as broadcast vectors
+// (readlanes would occupy the VALU).  The pivot lane holds d itself, so scaling every lane by
+// rsq(d) leaves sqrt(d) on the diagonal.  The whole panel is written back: entries above the
+// diagonal of the tile are never read.
 template <typename R, int P>
-__device__ int panel_factor(R* A, R* rdiag) {
+__device__ int panel_factor(R* A, R* rdiag, R* colbuf) {
   constexpr int STR = Mfma<R>::STR;
   constexpr int c0 = 16 * P;
   const int i = threadIdx.x & 63;
@@ -344,8 +345,35 @@ __device__ int panel_factor(R* A, R* rdiag) {
     const R r = rsq_full(bcast_lane(a[j], c0 + j));
     a[j] *= r;
     if (i == 0) rdiag[c0 + j] = r;
+    if (j + 1 < 16) {
+      // the next column's multiplier by readlane (it is on the chain); the later ones
+      // through LDS: every lane stores its a[j], and all read the 16 of the panel's rows back
+      // as broadcast vectors, off the chain and off the VALU
+      a[j + 1] = fma(-a[j], bcast_lane(a[j], c0 + j + 1), a[j + 1]);
+      if (j + 2 < 16) {
+        colbuf[j * 64 + i] = a[j];
+        R m[16];
+        if constexpr (sizeof(R) == 4) {
 #pragma unroll
-    for (int jj = j + 1; jj < 16; ++jj) a[jj] = fma(-a[j], bcast_lane(a[j], c0 + jj), a[jj]);
+          for (int q = 0; q < 4; ++q) {
+            const f32x4 t = *reinterpret_cast<const f32x4*>(colbuf + j * 64 + c0 + 4 * q);
+            m[4 * q] = t[0];
+            m[4 * q + 1] = t[1];
+            m[4 * q + 2] = t[2];
+            m[4 * q + 3] = t[3];
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const f64x2 t = *reinterpret_cast<const f64x2*>(colbuf + j * 64 + c0 + 2 * q);
+            m[2 * q] = t[0];
+            m[2 * q + 1] = t[1];
+          }
+        }
+#pragma unroll
+        for (int jj = j + 2; jj < 16; ++jj) a[jj] = fma(-a[j], m[jj], a[jj]);
+      }
+    }
   }
 #pragma unroll
   for (int j = 0; j < 16; ++j) A[i * STR + c0 + j] = a[j];
@@ -394,24 +422,65 @@ __device__ __forceinline__ void block_update(R* A, int br, int bc, int P) {
 
 // One wave: X_bb = L_bb^{-1} of diagonal 16x16 block b by forward substitution, lane c < 16
 // taking column c; the right-hand side e_c is formed arithmetically (no per-row lane masks).
+// FP32: the block's lower triangle and the pivot reciprocals are read from LDS first, as
+// 16-byte vectors, so the substitution waits for LDS once rather than once per row (in FP64
+// the 120 values would take 240 registers, and the rows are read as they are needed).
 template <typename R>
 __device__ __forceinline__ void diag_inverse(const R* A, R* X, const R* rdiag, int b) {
   constexpr int STR = Mfma<R>::STR;
   const int lane = threadIdx.x & 63;
+  if constexpr (sizeof(R) == 8) {
+    if (lane < 16) {
+      const int b0 = 16 * b, c = lane;
+      R x[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const R* rowi = A + (b0 + i) * STR + b0;
+        R d0 = 0, d1 = 0;
+#pragma unroll
+        for (int k = 0; k < i; k += 2) {
+          d0 = fma(rowi[k], x[k], d0);
+          if (k + 1 < i) d1 = fma(rowi[k + 1], x[k + 1], d1);
+        }
+        const R e = (R)(1 - min(abs(i - c), 1));
+        x[i] = (e - (d0 + d1)) * rdiag[b0 + i];
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) X[(b0 + i) * STR + b0 + c] = x[i];
+    }
+    return;
+  }
+  constexpr int V = 16 / (int)sizeof(R);            // elements per 16-byte vector
   if (lane < 16) {
     const int b0 = 16 * b, c = lane;
+    R L[16][16];
+#pragma unroll
+    for (int i = 1; i < 16; ++i) {
+#pragma unroll
+      for (int k0 = 0; k0 < i; k0 += V) {
+        const f32x4 t = *reinterpret_cast<const f32x4*>(A + (b0 + i) * STR + b0 + k0);
+#pragma unroll
+        for (int w = 0; w < V; ++w) L[i][k0 + w] = t[w];
+      }
+    }
+    R rd[16];
+#pragma unroll
+    for (int k0 = 0; k0 < 16; k0 += V) {
+      const f32x4 t = *reinterpret_cast<const f32x4*>(rdiag + b0 + k0);
+#pragma unroll
+      for (int w = 0; w < V; ++w) rd[k0 + w] = t[w];
+    }
     R x[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-      const R* rowi = A + (b0 + i) * STR + b0;
       R d0 = 0, d1 = 0;
 #pragma unroll
       for (int k = 0; k < i; k += 2) {
-        d0 = fma(rowi[k], x[k], d0);
-        if (k + 1 < i) d1 = fma(rowi[k + 1], x[k + 1], d1);
+        d0 = fma(L[i][k], x[k], d0);
+        if (k + 1 < i) d1 = fma(L[i][k + 1], x[k + 1], d1);
       }
       const R e = (R)(1 - min(abs(i - c), 1));
-      x[i] = (e - (d0 + d1)) * rdiag[b0 + i];
+      x[i] = (e - (d0 + d1)) * rd[i];
     }
 #pragma unroll
     for (int i = 0; i < 16; ++i) X[(b0 + i) * STR + b0 + c] = x[i];
@@ -455,16 +524,17 @@ __device__ __forceinline__ void offdiag_inverse(const R* A, R* X, int i, int j) 
 template <typename R>
 __device__ int cholinv_tile(R* A, R* X, R* rdiag) {
   __shared__ int s_bad;
+  __shared__ __align__(16) R colbuf[14 * 64];     // panel columns 0..13 (multipliers)
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   int bad = 0;
-  if (wv == 0) bad |= panel_factor<R, 0>(A, rdiag);
+  if (wv == 0) bad |= panel_factor<R, 0>(A, rdiag, colbuf);
   __syncthreads();
   if (wv == 0) {
     block_update<R>(A, 1, 1, 0);
     block_update<R>(A, 2, 1, 0);
     block_update<R>(A, 3, 1, 0);
     wave_sync_lds();
-    bad |= panel_factor<R, 1>(A, rdiag);
+    bad |= panel_factor<R, 1>(A, rdiag, colbuf);
   } else if (wv == 1) {
     block_update<R>(A, 2, 2, 0);
     block_update<R>(A, 3, 2, 0);
@@ -478,7 +548,7 @@ __device__ int cholinv_tile(R* A, R* X, R* rdiag) {
     block_update<R>(A, 2, 2, 1);
     block_update<R>(A, 3, 2, 1);
     wave_sync_lds();
-    bad |= panel_factor<R, 2>(A, rdiag);
+    bad |= panel_factor<R, 2>(A, rdiag, colbuf);
   } else if (wv == 1) {
     block_update<R>(A, 3, 3, 1);
   } else if (wv == 2) {
@@ -488,7 +558,7 @@ __device__ int cholinv_tile(R* A, R* X, R* rdiag) {
   if (wv == 0) {
     block_update<R>(A, 3, 3, 2);
     wave_sync_lds();
-    bad |= panel_factor<R, 3>(A, rdiag);
+    bad |= panel_factor<R, 3>(A, rdiag, colbuf);
     if (lane == 0) s_bad = bad;
   } else if (wv == 1) {
     diag_inverse<R>(A, X, rdiag, 2);
@@ -974,7 +1044,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
   using acc_t = typename Mfma<R>::acc_t;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R* lds = reinterpret_cast<R*>(smem_raw);            // 4 tiles
-  __shared__ R rdiag[64];
+  __shared__ __align__(16) R rdiag[64];
   __shared__ double s_vec[64];
   __shared__ double s_red[kThreads];
   const int tid = threadIdx.x, wv = tid >> 6;

@@ -430,20 +430,34 @@ __device__ __forceinline__ void diag_inverse(const R* A, R* X, const R* rdiag, i
   constexpr int STR = Mfma<R>::STR;
   const int lane = threadIdx.x & 63;
   if constexpr (sizeof(R) == 8) {
+    // FP64: each row's part of the block and its pivot reciprocal are read one row ahead, as
+    // 16-byte vectors, so that the substitution of a row does not wait for its own reads
     if (lane < 16) {
       const int b0 = 16 * b, c = lane;
-      R x[16];
+      R x[16], cur[16], nxt[16], rcur, rnxt;
+      rcur = rdiag[b0];
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
-        const R* rowi = A + (b0 + i) * STR + b0;
+        if (i + 1 < 16) {
+#pragma unroll
+          for (int k0 = 0; k0 < i + 1; k0 += 2) {
+            const f64x2 t = *reinterpret_cast<const f64x2*>(A + (b0 + i + 1) * STR + b0 + k0);
+            nxt[k0] = t[0];
+            nxt[k0 + 1] = t[1];
+          }
+          rnxt = rdiag[b0 + i + 1];
+        }
         R d0 = 0, d1 = 0;
 #pragma unroll
         for (int k = 0; k < i; k += 2) {
-          d0 = fma(rowi[k], x[k], d0);
-          if (k + 1 < i) d1 = fma(rowi[k + 1], x[k + 1], d1);
+          d0 = fma(cur[k], x[k], d0);
+          if (k + 1 < i) d1 = fma(cur[k + 1], x[k + 1], d1);
         }
         const R e = (R)(1 - min(abs(i - c), 1));
-        x[i] = (e - (d0 + d1)) * rdiag[b0 + i];
+        x[i] = (e - (d0 + d1)) * rcur;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) cur[k] = nxt[k];
+        rcur = rnxt;
       }
 #pragma unroll
       for (int i = 0; i < 16; ++i) X[(b0 + i) * STR + b0 + c] = x[i];

@@ -30,8 +30,9 @@
 // flags and messages, so the kernel needs no host-side clearing between launches.
 //
 // The factor is stored tile-packed (column-major over the tiles of the lower triangle,
-// row-major inside a tile) next to the inverses of the diagonal tiles, which the
-// triangular solves use as small dense products.  Forward and backward substitution use the
+// row-major inside a tile while it is built; after the factorisation k_transpose_tiles
+// rewrites every tile in the solves' layout and writes their transposed copies) next to the
+// inverses of the diagonal tiles, which the triangular solves use as small dense products.  Forward and backward substitution use the
 // same ticket scheme over 64-row blocks, with message hand-offs.  In mixed precision the
 // factor and the products run in FP32 (FP32 MFMA); right-hand sides, solutions and the
 // refinement residual g - (H + mu I) d are FP64.

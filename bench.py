@@ -461,6 +461,15 @@ def main():
     breakdown = {name: ctx.timing(i) for i, name in enumerate(timer_names)}
     ctx.enable_timing(False)
     final_cost = infos[-1][-1].cost if infos else None   # residual cost after the last visit
+    visits = [i for row in (infos or []) for i in row]
+    lm_stats = {
+        "accepted": int(sum(i.n_accept for i in visits)),
+        "rejected": int(sum(i.n_reject for i in visits)),
+        "failed_factorisations": int(sum(i.n_notpd for i in visits)),
+        "max_refinement_steps": int(max((i.max_refine for i in visits), default=0)),
+        "note": "over the 600 LM iterations of the step that collects the kernel breakdown; "
+                "refinement steps are the FP64 corrections of one iteration (at most refine_max)",
+    }
 
     ms_per_step = 1e3 * elapsed / args.steps
     value = n_lm_per_step * args.steps / elapsed
@@ -506,6 +515,7 @@ def main():
         "kernels_note": "per-kernel HIP-event times from one extra step with every kernel class "
                         "timed (the timed steps time only the factorisation and the predict)",
         "final_total_cost": final_cost,
+        "lm": lm_stats,
     }
 
     # station-factorised predict of the same sky (same coherencies; reported beside the

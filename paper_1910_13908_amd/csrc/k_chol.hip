@@ -1484,6 +1484,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
   __shared__ double s_vec[64];
   constexpr int D = chain_d<R>();
   __shared__ double s_y[2][64];   // the last two solution blocks
+  __shared__ double sxb[2][64];   // a helper's two polled solution blocks
   // a gated launch touches nothing (counters and message slots stay as the last solve left
   // them), so its workgroups just leave
   if (gated(lm, gate)) return;
@@ -1602,7 +1603,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
       }
     } else {
       // helper for the block at solve position q = t + D - 1: contributions of positions
-      // 0 .. q-D, two solution blocks fetched per poll
+      // 0 .. q-D, two solution blocks polled at a time by one wave
       const int q = (int)t + D - 1;
       const int I = solve_block<FWD>(T, q);
       const int last = q - D;
@@ -1626,22 +1627,15 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
         double x0[16], x1[16];
         uint32_t spins = 0;
         for (;;) {
-          // one lane watches the last entry of the newer block (a short bounded poll), so the
-          // helpers do not all keep re-reading the lines the worker is writing; every entry is
-          // then fetched and checked, as the entries need not appear in order
-          if (tid == 0) {
-            for (int sp = 0; sp < 4096 && msg_get(xpub + 64 * K1 + 63) == kEmpty; ++sp)
-              __builtin_amdgcn_s_sleep(2);
-          }
-          __syncthreads();
+          // wave 0 polls both blocks whole (one entry per lane and block, one round trip per
+          // poll) and leaves them in LDS for the other waves
           bool miss = false;
-#pragma unroll
-          for (int u = 0; u < 16; ++u) {
-            const uint64_t m0 = msg_get(xpub + 64 * K0 + part * 16 + u);
-            const uint64_t m1 = msg_get(xpub + 64 * K1 + part * 16 + u);
-            miss |= (m0 == kEmpty) | (m1 == kEmpty);
-            x0[u] = __longlong_as_double((long long)m0);
-            x1[u] = __longlong_as_double((long long)m1);
+          if (tid < 64) {
+            const uint64_t m0 = msg_get(xpub + 64 * K0 + tid);
+            const uint64_t m1 = msg_get(xpub + 64 * K1 + tid);
+            miss = (m0 == kEmpty) | (m1 == kEmpty);
+            sxb[0][tid] = __longlong_as_double((long long)m0);
+            sxb[1][tid] = __longlong_as_double((long long)m1);
           }
           if (!__syncthreads_or(miss) || !live) break;
           if (tid == 0) {
@@ -1659,6 +1653,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
           __syncthreads();
           __builtin_amdgcn_s_sleep(2);
         }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          x0[u] = sxb[0][part * 16 + u];
+          x1[u] = sxb[1][part * 16 + u];
+        }
+        __syncthreads();     // the next poll rewrites sxb
 #pragma unroll
         for (int u = 0; u < 16; ++u) acc = fma((double)c0[u], x0[u], acc);
         if (two) {

@@ -1369,19 +1369,19 @@ __device__ __forceinline__ double reduce4(double v, double* sh) {
 // the first of which is then complete.  The other workgroups (helpers, one per block from
 // solve position D on) accumulate the contributions of all blocks at distance >= D as their
 // solutions appear and hand the 64-entry partial sum to the worker, which has D-1 steps of
-// slack (D = chain_d<R> = 4: the worker streams D tiles per step through its one compute
-// unit, so a larger D slows every step).  In the worker the four 16-column parts of a row sit
+// slack (D = chain_d<R> = 3: the worker streams D tiles per step through its one compute
+// unit, so a larger D slows every step, and a smaller one leaves the hand-off too little).  In the worker the four 16-column parts of a row sit
 // in adjacent lanes of one wave, so a row sum is two DPP exchanges in a fixed order and a
 // step needs two workgroup barriers.
 // Hand-offs carry the data itself: solution blocks and partial sums travel through two
 // message arrays written and read with agent-scope relaxed 64-bit atomics, and a slot that
 // still holds kEmpty (a signalling-NaN payload that no arithmetic result carries) is not
 // ready yet.  So there is no fence or flag on the chain.  The worker fetches the partial sum
-// of the block two steps ahead; a helper watches one entry with one lane before fetching
-// whole blocks, which keeps the polling off the lines the worker writes.  The last workgroup
-// out restores kEmpty in both arrays.
+// of a block a step ahead; a helper polls the solution blocks it waits for with one wave, one
+// entry per lane, which keeps the polling off most of the lines the worker writes.  The last
+// workgroup out restores kEmpty in both arrays.
 template <typename R>
-constexpr int chain_d() { return 4; }
+constexpr int chain_d() { return 3; }
 // Register slots of the chain worker's operands (prefetch depth + 1): three in FP32, two in
 // FP64, where the operands take twice the registers.
 template <typename R>

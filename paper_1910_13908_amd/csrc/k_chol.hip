@@ -1245,7 +1245,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
       if constexpr (sizeof(R) == 4) {
         TileRegs<R> xr;
         const uint64_t* tx = tile_slots(part_raw, T, tile_index(J, J, T));
-        const bool g = tagged_watch(tx, seq, sync, status) &&
+        // the tile two below the diagonal feeds the next look-ahead tasks: it polls the inverse
+        // whole (one round trip sooner); the others watch one slot first
+        const bool g = (I == J + 2 || tagged_watch(tx, seq, sync, status)) &&
                        tagged_tile_fetch(tx, seq, xr, sync, status);
         ok = __syncthreads_and(ok && g) != 0;
         tile_stash<R>(xr, lds + TILE);

@@ -170,6 +170,9 @@ ddc_status ddc_predict_factored(ddc_ctx* ctx, const ddc_obs* obs, const double* 
  * f = ||res||^2, accumulated in FP64 in a fixed order.
  * vis, res: 8 planes [T][F][B]; coh: [K][8][T][F][B]; jones: [K][N][8].
  * res may be NULL (cost only); cost (HOST) may be NULL (no sync); res may alias vis.
+ * With K >= 2 the workspace also holds a copy of the Jones matrices as K*8 component planes
+ * (K*8*N elements, same values) that the kernel reads coalesced; the first call that needs
+ * more workspace grows it, which synchronises the stream.
  * DDC_ENONFINITE if the cost is requested and is NaN/Inf (res is still written). */
 ddc_status ddc_residual(ddc_ctx* ctx, const ddc_obs* obs, int32_t n_clusters, const void* vis,
                         const void* coh, const double* jones, int32_t precision,
@@ -192,7 +195,7 @@ ddc_status ddc_residual_noalloc(ddc_ctx* ctx, const ddc_obs* obs, int32_t n_clus
 /* out = in + alpha * sum_{k<K} J_k C_k J_k^H (alpha = +1 or -1); out may alias in: the
  * model of clusters 0..K-1 (paper Section 2, one Jones solution per cluster) added to or
  * taken from visibility planes.  Used to form synthetic data (in = noise) and the
- * per-cluster data of a SAGE sweep. */
+ * per-cluster data of a SAGE sweep.  Workspace as for ddc_residual (Jones planes, K >= 2). */
 ddc_status ddc_add_model(ddc_ctx* ctx, const ddc_obs* obs, int32_t n_clusters, const void* in,
                          const void* coh, const double* jones, double alpha,
                          int32_t precision, void* out);

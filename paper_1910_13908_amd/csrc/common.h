@@ -134,10 +134,12 @@ inline int64_t residual_blocks(const ResidualJob& j) { return (j.plane + 255) / 
 template <typename R>
 hipError_t launch_residual_batch(const ResidualJob* jobs_dev, int njobs, int64_t total_blocks,
                                  int grid, hipStream_t st);
+// jplanes (optional, 8 (k1 - k0) N elements): workspace for the Jones matrices as component
+// planes when k1 - k0 >= 2 (same results, coalesced reads)
 template <typename R>
 hipError_t launch_add_model(const ObsDev& o, int k0, int k1, const R* in, const R* coh,
                             const double* jones, double alpha, R* out, double* cost_part,
-                            int* nblk, hipStream_t st);
+                            int* nblk, hipStream_t st, R* jplanes = nullptr);
 hipError_t launch_sum(const double* parts, int n, double* out, hipStream_t st);
 template <typename R>
 hipError_t launch_build_neq(const ObsDev& o, const R* y, const R* coh, const double* jones,

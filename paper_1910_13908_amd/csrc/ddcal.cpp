@@ -169,6 +169,15 @@ ddc_status ensure_ws(ddc_ctx* c, size_t bytes) {
   return DDC_OK;
 }
 
+// Workspace for a call outside the solve layout (predict phasors, residual, cost gradient).
+// Such a call may overwrite the matrix storage, whose zeros and padding diagonal are written
+// once per (address, size), so the next solve writes them again.
+ddc_status ensure_ws_other(ddc_ctx* c, size_t bytes) {
+  DDCCK(ensure_ws(c, bytes));
+  c->h_ptr = nullptr;
+  return DDC_OK;
+}
+
 ddc_status check_prec(ddc_ctx* c, int32_t p) {
   if (p != DDC_FP64 && p != DDC_MIXED) return fail(c, DDC_EINVAL, "precision must be DDC_FP64 or DDC_MIXED");
   return DDC_OK;
@@ -490,7 +499,7 @@ ddc_status ddc_predict(ddc_ctx* c, const ddc_obs* obs, const ddc_sky* sky, int32
     return fail(c, DDC_EINVAL, "sky arrays must not be NULL");
   Bump bp;
   const size_t off = bp.take((size_t)(K + 1) * sizeof(int32_t));
-  DDCCK(ensure_ws(c, bp.off));
+  DDCCK(ensure_ws_other(c, bp.off));
   int32_t* offs = reinterpret_cast<int32_t*>(c->ws + off);
   HIPCK(hipMemcpyAsync(offs, sky->cluster_offset, (K + 1) * sizeof(int32_t), hipMemcpyHostToDevice,
                        c->stream));
@@ -531,7 +540,7 @@ ddc_status ddc_predict_factored(ddc_ctx* c, const ddc_obs* obs, const double* su
   Bump bp;
   const size_t off = bp.take((size_t)(K + 1) * sizeof(int32_t));
   const size_t off_e = bp.take(phasor_bytes(o.N, S, o.T, o.F, es));
-  DDCCK(ensure_ws(c, bp.off));
+  DDCCK(ensure_ws_other(c, bp.off));
   int32_t* offs = reinterpret_cast<int32_t*>(c->ws + off);
   void* E = c->ws + off_e;
   HIPCK(hipMemcpyAsync(offs, sky->cluster_offset, (K + 1) * sizeof(int32_t), hipMemcpyHostToDevice,
@@ -561,19 +570,33 @@ ddc_status add_model_impl(ddc_ctx* c, const ObsDev& o, int K, const void* in, co
   const int64_t nblk = (plane + 255) / 256;
   double* parts = nullptr;
   double* total = nullptr;
-  if (cost) {
+  R* jplanes = nullptr;
+  {
+    // cost partials, and the Jones matrices as component planes when K >= 2 (left out, and
+    // the Jones matrices read in place, when a lent workspace has no room for them)
     Bump bp;
-    const size_t o1 = bp.take((size_t)nblk * sizeof(double));
-    const size_t o2 = bp.take(64);
-    DDCCK(ensure_ws(c, bp.off));
-    parts = reinterpret_cast<double*>(c->ws + o1);
-    total = reinterpret_cast<double*>(c->ws + o2);
+    const size_t o1 = cost ? bp.take((size_t)nblk * sizeof(double)) : 0;
+    const size_t o2 = cost ? bp.take(64) : 0;
+    const size_t without = bp.off;
+    bool planar = K >= 2;
+    const size_t o3 = planar ? bp.take((size_t)K * 8 * o.N * sizeof(R)) : 0;
+    if (planar && c->ws_external && bp.off > c->ws_bytes) {
+      planar = false;
+      bp.off = without;
+    }
+    if (bp.off) DDCCK(ensure_ws_other(c, bp.off));
+    if (cost) {
+      parts = reinterpret_cast<double*>(c->ws + o1);
+      total = reinterpret_cast<double*>(c->ws + o2);
+    }
+    if (planar) jplanes = reinterpret_cast<R*>(c->ws + o3);
   }
   int nb = 0;
   const double bytes = (double)plane * (16.0 + 8.0 * K) * sizeof(R);
   DDCCK(timed(c, T_MODEL, bytes, [&] {
     return launch_add_model<R>(o, 0, K, reinterpret_cast<const R*>(in), reinterpret_cast<const R*>(coh),
-                               jones, alpha, reinterpret_cast<R*>(out), parts, &nb, c->stream);
+                               jones, alpha, reinterpret_cast<R*>(out), parts, &nb, c->stream,
+                               jplanes);
   }));
   if (cost) {
     HIPCK(launch_sum(parts, nb, total, c->stream));
@@ -1031,7 +1054,7 @@ ddc_status cost_gradient_impl(ddc_ctx* c, const ObsDev& o, int K, const void* vi
   const size_t o_part = bp.take((size_t)K * 16 * o.B * sizeof(R));
   const size_t o_cp = bp.take((size_t)nblk * sizeof(double));
   const size_t o_tot = bp.take(64);
-  DDCCK(ensure_ws(c, bp.off));
+  DDCCK(ensure_ws_other(c, bp.off));
   R* res = reinterpret_cast<R*>(c->ws + o_res);
   R* part = reinterpret_cast<R*>(c->ws + o_part);
   double* cp = reinterpret_cast<double*>(c->ws + o_cp);

@@ -88,6 +88,16 @@ __device__ __forceinline__ M2<R> load_jones(const double* __restrict__ J, int st
   return o;
 }
 
+// The same Jones matrix from component planes (plane c holds component c of every station,
+// already rounded to R): equal values, one coalesced load per component across a wave.
+template <typename R>
+__device__ __forceinline__ M2<R> load_jones_planes(const R* __restrict__ P, int64_t N, int st) {
+  M2<R> o;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) o.e[e] = {P[(2 * e) * N + st], P[(2 * e + 1) * N + st]};
+  return o;
+}
+
 // (J + d) for the trial step, summed in FP64 before rounding to R.
 template <typename R>
 __device__ __forceinline__ M2<R> load_jones_step(const double* __restrict__ J,
@@ -138,18 +148,27 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 // out = in + alpha * sum_{k in [k0,k1)} J_k C_k J_k^H; optional cost partials of ||out||^2.
 // ---------------------------------------------------------------------------------------
 // One element i of out = in + alpha * sum_k J_k C_k J_k^H; returns ||out_i||^2.  Shared by
-// the single-problem kernel and the batched one, so both round identically.
-template <typename R>
+// the single-problem kernel and the batched one, so both round identically.  With PL the
+// Jones matrices come from jpl, the component planes of clusters k0.. (the same values).
+template <typename R, bool PL = false>
 __device__ __forceinline__ double add_model_elem(
     const R* __restrict__ in, const R* __restrict__ coh, const double* __restrict__ jones,
-    const int32_t* __restrict__ ant_p, const int32_t* __restrict__ ant_q, int64_t B,
-    int64_t plane, int N, int k0, int k1, R alpha, R* __restrict__ out, int64_t i) {
+    const R* __restrict__ jpl, const int32_t* __restrict__ ant_p,
+    const int32_t* __restrict__ ant_q, int64_t B, int64_t plane, int N, int k0, int k1,
+    R alpha, R* __restrict__ out, int64_t i) {
   const int64_t b = i % B;
   const int p = ant_p[b], q = ant_q[b];
   M2<R> acc = load_vis(in, plane, i);
   for (int k = k0; k < k1; ++k) {
-    const M2<R> Jp = load_jones<R>(jones + (int64_t)k * 8 * N, p);
-    const M2<R> Jq = load_jones<R>(jones + (int64_t)k * 8 * N, q);
+    M2<R> Jp, Jq;
+    if constexpr (PL) {
+      const R* P = jpl + (int64_t)(k - k0) * 8 * N;
+      Jp = load_jones_planes<R>(P, N, p);
+      Jq = load_jones_planes<R>(P, N, q);
+    } else {
+      Jp = load_jones<R>(jones + (int64_t)k * 8 * N, p);
+      Jq = load_jones<R>(jones + (int64_t)k * 8 * N, q);
+    }
     const M2<R> C = load_vis(coh + (int64_t)k * 8 * plane, plane, i);
     const M2<R> M = mmul_bh(mmul(Jp, C), Jq);
 #pragma unroll
@@ -168,20 +187,36 @@ __device__ __forceinline__ double add_model_elem(
   return norm2(acc);
 }
 
-template <typename R>
+template <typename R, bool PL>
 __global__ __launch_bounds__(kThreads) void k_add_model(
     const R* __restrict__ in, const R* __restrict__ coh, const double* __restrict__ jones,
-    const int32_t* __restrict__ ant_p, const int32_t* __restrict__ ant_q, int64_t B,
-    int64_t plane, int N, int k0, int k1, R alpha, R* __restrict__ out,
-    double* __restrict__ cost_part) {
+    const R* __restrict__ jpl, const int32_t* __restrict__ ant_p,
+    const int32_t* __restrict__ ant_q, int64_t B, int64_t plane, int N, int k0, int k1,
+    R alpha, R* __restrict__ out, double* __restrict__ cost_part) {
   __shared__ double sh[kThreads / 64];
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   double cst = 0.0;
-  if (i < plane) cst = add_model_elem<R>(in, coh, jones, ant_p, ant_q, B, plane, N, k0, k1, alpha, out, i);
+  if (i < plane)
+    cst = add_model_elem<R, PL>(in, coh, jones, jpl, ant_p, ant_q, B, plane, N, k0, k1, alpha,
+                                out, i);
   if (cost_part) {
     const double s = block_sum(cst, sh);
     if (threadIdx.x == 0) cost_part[blockIdx.x] = s;
   }
+}
+
+// Jones matrices of nk clusters (station-major, 8 doubles per station) as component planes
+// rounded to R: planes[(k * 8 + c) * N + n] = J_k[n][c].  A wave's gather of 64 stations'
+// 64-byte records touches 32 cache lines per 16-byte load; from the planes each component
+// is one coalesced load.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_jones_planes(const double* __restrict__ jones,
+                                                           int N, int nk, R* __restrict__ planes) {
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (t >= (int64_t)nk * 8 * N) return;
+  const int64_t kc = t / N;
+  const int64_t n = t - kc * N;
+  planes[t] = (R)jones[((kc >> 3) * N + n) * 8 + (kc & 7)];
 }
 
 // Initial residuals of several solves in one persistent launch: the workgroups walk the
@@ -197,7 +232,7 @@ __global__ __launch_bounds__(kThreads) void k_residual_batch(const ResidualJob* 
     const int64_t i = (vb - j.first_block) * kThreads + threadIdx.x;
     if (i < j.plane)
       (void)add_model_elem<R>(reinterpret_cast<const R*>(j.vis), reinterpret_cast<const R*>(j.coh),
-                              j.jones, j.ant_p, j.ant_q, j.B, j.plane, j.N, 0, j.K, (R)-1,
+                              j.jones, nullptr, j.ant_p, j.ant_q, j.B, j.plane, j.N, 0, j.K, (R)-1,
                               reinterpret_cast<R*>(j.out), i);
   }
 }
@@ -501,12 +536,25 @@ __global__ __launch_bounds__(kThreads) void k_sum(const double* __restrict__ par
 template <typename R>
 hipError_t launch_add_model(const ObsDev& o, int k0, int k1, const R* in, const R* coh,
                             const double* jones, double alpha, R* out, double* cost_part,
-                            int* nblk, hipStream_t st) {
+                            int* nblk, hipStream_t st, R* jplanes) {
   const int64_t plane = (int64_t)o.T * o.F * o.B;
   const unsigned g = (unsigned)((plane + kThreads - 1) / kThreads);
   if (nblk) *nblk = (int)g;
-  hipLaunchKernelGGL(k_add_model<R>, dim3(g), dim3(kThreads), 0, st, in, coh, jones, o.ant_p,
-                     o.ant_q, o.B, plane, o.N, k0, k1, (R)alpha, out, cost_part);
+  // several clusters: their Jones matrices are read from component planes
+  const R* jpl = nullptr;
+  if (jplanes && k1 - k0 >= 2) {
+    const int64_t n = (int64_t)(k1 - k0) * 8 * o.N;
+    hipLaunchKernelGGL(k_jones_planes<R>, dim3((unsigned)((n + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, st, jones + (int64_t)k0 * 8 * o.N, o.N, k1 - k0,
+                       jplanes);
+    jpl = jplanes;
+  }
+  if (jpl)
+    hipLaunchKernelGGL((k_add_model<R, true>), dim3(g), dim3(kThreads), 0, st, in, coh, jones,
+                       jpl, o.ant_p, o.ant_q, o.B, plane, o.N, k0, k1, (R)alpha, out, cost_part);
+  else
+    hipLaunchKernelGGL((k_add_model<R, false>), dim3(g), dim3(kThreads), 0, st, in, coh, jones,
+                       jpl, o.ant_p, o.ant_q, o.B, plane, o.N, k0, k1, (R)alpha, out, cost_part);
   return hipGetLastError();
 }
 
@@ -571,7 +619,7 @@ hipError_t launch_cost_adjoint(const ObsDev& o, int K, const R* res, const R* co
                                                hipStream_t);                                   \
   template hipError_t launch_add_model<R>(const ObsDev&, int, int, const R*, const R*,        \
                                           const double*, double, R*, double*, int*,           \
-                                          hipStream_t);                                       \
+                                          hipStream_t, R*);                                   \
   template hipError_t launch_build_neq<R>(const ObsDev&, const R*, const R*, const double*,   \
                                           R*, int, R*, double*, int*, const LMState*,          \
                                           hipStream_t);                                       \

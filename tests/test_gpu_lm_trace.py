@@ -16,6 +16,9 @@ failure paths, through the C ABI.
 * With the inter-workgroup waits bounded at one retry (ddc_set_wait_limit), the solves time
   out and the calls report DDC_ETIMEOUT with the Jones untouched; the context then solves
   normally.  Every kernel still leaves normally: the bound only makes waits give up sooner.
+* Calls that put their own buffers in the context's workspace (the residual, the cost
+  gradient) between two solves leave the later solve bit-identical to a fresh context's,
+  with N = 10 (matrix storage padded from 80 to 128 rows).
 """
 import math
 
@@ -211,3 +214,36 @@ def test_wait_timeout_is_reported_and_the_context_recovers(dd, n64, prec):
         assert abs(info.cost - io.cost) <= (1e-9 if prec == 0 else 1e-5) * io.cost
     finally:
         ctx.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
+def test_other_calls_between_solves_leave_them_unchanged(dd, prec):
+    # The residual (with its Jones planes) and the cost gradient use the context's workspace
+    # for their own buffers, over the matrix storage whose zeros and padding diagonal a solve
+    # writes once.  With N = 10 (8N = 80 rows padded to 128) a later solve on the same context
+    # must still equal, bit for bit, the same solve on a fresh context.
+    import torch
+    cfg = synth.ObsConfig(10, 2, 3, 2, (150e6,))
+    ob, V, C = setup(cfg, seed=7)
+    a, b = dd.Context(0), dd.Context(0)
+    try:
+        d = to_dev(dd, ob, prec, V=V)
+        coh = a.predict(d["obs"], d["sky"], prec)
+        J0 = torch.as_tensor(dd.jones_real(synth.identity_jones(2, ob.N)), device="cuda").contiguous()
+        opts = dd.default_lm_opts(n_iter=4, precision=prec)
+        Ja = J0.clone()
+        ia = a.lm_solve(d["obs"], d["V"], coh[0].contiguous(), Ja[0], opts)
+        Jb = J0.clone()
+        b.lm_solve(d["obs"], d["V"], coh[0].contiguous(), Jb[0], opts)
+        b.residual(d["obs"], 2, d["V"], coh, J0, prec, want_cost=False)
+        b.cost_gradient(d["obs"], 2, d["V"], coh, J0, prec)
+        Jb = J0.clone()
+        ib = b.lm_solve(d["obs"], d["V"], coh[0].contiguous(), Jb[0], opts)
+        torch.cuda.synchronize()
+        assert ia.n_accept >= 1
+        assert (ib.n_accept, ib.n_reject) == (ia.n_accept, ia.n_reject)
+        assert ib.cost == ia.cost
+        assert torch.equal(Ja, Jb)
+    finally:
+        a.close()
+        b.close()

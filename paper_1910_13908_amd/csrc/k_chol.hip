@@ -1678,8 +1678,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
 // Refinement residual s = g - (H + mu I) d in FP64 from the FP32/FP64 column-major lower
 // storage.  Pass 1: one workgroup per lower tile (I, J) writes its two contributions,
 // H_IJ d_J (to rows of block I) and, off the diagonal, H_IJ^T d_I (to rows of block J), into
-// per-tile partials; reads follow the storage's contiguous columns.  Pass 2: one workgroup
-// per block row sums the partials in a fixed order, so the result is deterministic.
+// per-tile partials; the tile is read once, along the storage's contiguous columns, and the
+// transposed product takes it from LDS.  Pass 2: one workgroup per block row sums the
+// partials in a fixed order, so the result is deterministic.
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_symv_tiles(
     const R* __restrict__ Hc, int64_t ld, int T, const double* __restrict__ d,
@@ -1689,6 +1690,7 @@ __global__ __launch_bounds__(kThreads) void k_symv_tiles(
   __shared__ double sd_col[64];   // d_J
   __shared__ double sd_row[64];   // d_I
   __shared__ double sh[kThreads];
+  __shared__ R tt[64][65];        // off-diagonal tile, tt[c][r] = H[r][c] (padded: no conflicts)
   int I = 0, J = 0;
   {
     // blockIdx.x enumerates the lower tiles column-major
@@ -1703,8 +1705,7 @@ __global__ __launch_bounds__(kThreads) void k_symv_tiles(
   }
   const int tid = threadIdx.x, r = tid & 63, part = tid >> 6;
   const R* base = Hc + (int64_t)(64 * J) * ld + 64 * I;   // element (row r, col c) at c*ld + r
-  // every H load of the tile (both products) is issued before the first barrier
-  R hv[16], cv[16];
+  R hv[16];
 #pragma unroll
   for (int cc = 0; cc < 16; ++cc) {
     // rows of block I: H[r][c] for the 16 columns of this part; on the diagonal tile the
@@ -1712,15 +1713,15 @@ __global__ __launch_bounds__(kThreads) void k_symv_tiles(
     const int cl = part * 16 + cc;
     hv[cc] = (I != J || cl <= r) ? base[(int64_t)cl * ld + r] : base[(int64_t)r * ld + cl];
   }
-  if (I != J) {
-    // rows of block J: column c of the tile, 16 contiguous rows
-    const R* col = base + (int64_t)r * ld + part * 16;
-#pragma unroll
-    for (int rr = 0; rr < 16; ++rr) cv[rr] = col[rr];
-  }
   if (tid < 64) {
     sd_col[tid] = d[64 * J + tid];
     sd_row[tid] = d[64 * I + tid];
+  }
+  // off the diagonal the same elements serve the rows of block J through LDS (read per lane
+  // from global memory, each load touched 64 lines)
+  if (I != J) {
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc) tt[part * 16 + cc][r] = hv[cc];
   }
   __syncthreads();
   // rows of block I: sum_c H[r][c] d_J[c]
@@ -1730,10 +1731,11 @@ __global__ __launch_bounds__(kThreads) void k_symv_tiles(
   const double rowsum = reduce4(a, sh);
   if (tid < 64) prow[((int64_t)blockIdx.x) * 64 + tid] = rowsum;
   if (I != J) {
-    // rows of block J: sum_r H[r][c] d_I[r], c = tid & 63
+    // rows of block J: sum_r H[r][c] d_I[r], c = tid & 63, over the 16 rows of this part
     double b2 = 0.0;
 #pragma unroll
-    for (int rr = 0; rr < 16; ++rr) b2 = fma((double)cv[rr], sd_row[part * 16 + rr], b2);
+    for (int rr = 0; rr < 16; ++rr)
+      b2 = fma((double)tt[r][part * 16 + rr], sd_row[part * 16 + rr], b2);
     const double colsum = reduce4(b2, sh);
     if (tid < 64) pcol[((int64_t)blockIdx.x) * 64 + tid] = colsum;
   }

@@ -16,9 +16,10 @@ model of a baseline is affine in any single real parameter of one station, since
 joins a station to itself), the step by an augmented least-squares solve, and the predicted
 decrease as ||r||^2 - ||r - A d||^2 rather than the oracle's d . (mu d + g), which equals it only
 when the step solves the damped normal equations.  Each problem is chosen so that the quantity
-under test moves the result (a gain ratio well inside (0, 0.9), a clamped update, a genuine
-cost increase), so a dropped term, a square for the cube, a halved denominator, a missing
-doubling of nu or a moved floor each fail a test.
+under test moves the result (a gain ratio well inside (0, 0.9), a small positive one, a
+clamped update, a genuine cost increase), so a dropped term, a square for the cube, a halved
+denominator, a raised acceptance threshold, a missing doubling of nu or a moved floor each
+fail a test.
 """
 import numpy as np
 import pytest
@@ -119,6 +120,22 @@ def test_gain_ratio_and_accepted_damping_update():
     expect = mu * max(1.0 / 3.0, 1.0 - (2.0 * rho - 1.0) ** 3)
     assert abs(info.mu - expect) <= 1e-9 * expect, (info.mu, expect)
     assert info.mu > mu                       # rho < 1/2 raises the damping
+    assert info.nu == 2.0
+
+
+def test_small_positive_gain_ratio_is_accepted():
+    # any rho > 0 accepts the step (the cost went down, if by less than the linear model
+    # promised): here rho is about 0.07, and the update raises mu by 1 - (2 rho - 1)^3
+    ob, V, C, x0, r, A = _setup(1.2, 4)
+    md = float(np.max(np.sum(A * A, axis=0)))
+    mu = 1e-3 * md
+    d, f, f_new, rho = _gain_ratio(ob, V, C, x0, r, A, mu)
+    assert 0.0 < rho < 0.15, rho
+    J1, info = lm.lm_solve(V, C, _x_to_J(x0), ob.ant_p, ob.ant_q, n_iter=1, mu=mu, nu=4.0)
+    assert info.accepted == [True]
+    assert np.max(np.abs(_J_to_x(J1) - (x0 + d))) <= 1e-9 * np.max(np.abs(d))
+    expect = mu * max(1.0 / 3.0, 1.0 - (2.0 * rho - 1.0) ** 3)
+    assert abs(info.mu - expect) <= 1e-8 * expect, (info.mu, expect)
     assert info.nu == 2.0
 
 

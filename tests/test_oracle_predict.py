@@ -44,6 +44,17 @@ def test_quarter_turn_sign():
     assert abs(Cc[1, 0, 0] - 1.0j) < 1e-14
 
 
+def test_each_channel_takes_its_own_frequency():
+    # the phase scales with f: one baseline, a quarter turn at f, so the channels f, 2f, 3f
+    # and 4f see -i, -1, +i and +1 (the same u l, four frequencies in one call)
+    f = 150e6
+    l = 0.01
+    u = 0.25 * (C / f) / l
+    Cc = _one([u], [0.0], [0.0], [f, 2 * f, 3 * f, 4 * f], l, 0.0)[0, 0, :, 0, 0, 0]
+    for got, want in zip(Cc, (-1.0j, -1.0, 1.0j, 1.0)):
+        assert abs(got - want) < 1e-13, (got, want)
+
+
 def test_w_term_zero_at_centre_and_matches_sqrt():
     assert rime.n_minus_1(0.0, 0.0) == 0.0
     import mpmath

@@ -183,6 +183,23 @@ def test_zero_step_is_rejected():
     assert np.array_equal(J, J0)
 
 
+def test_zero_start_fails_to_factor_every_step():
+    # fresh start at J = 0: H = 0, so mu_0 = tau * max diag H = 0 and the floor is 0 too;
+    # the zero matrix has no Cholesky factor, so each iteration is a failed factorisation
+    # counted as a rejection (mu stays 0, nu doubles)
+    ob, V, C, x0, r, A = _setup(0.3, 2)
+    J0 = np.zeros((ob.N, 2, 2), dtype=np.complex128)
+    J, info = lm.lm_solve(V, C, J0, ob.ant_p, ob.ant_q, n_iter=3)
+    assert (info.n_notpd, info.n_reject, info.n_accept) == (3, 3, 0)
+    assert info.mu_effs == [0.0, 0.0, 0.0] and info.mus == [0.0, 0.0, 0.0]
+    assert info.nus == [4.0, 8.0, 16.0]
+    assert np.array_equal(J, J0)
+    fV = float(np.sum(np.abs(V) ** 2))
+    assert abs(info.cost - fV) <= 1e-12 * fV                      # f at J = 0 is ||V||^2
+    with pytest.raises(np.linalg.LinAlgError):
+        np.linalg.cholesky(np.zeros((8 * ob.N, 8 * ob.N)))
+
+
 @pytest.mark.parametrize("mu_rel, floor_active", [(1e-12, True), (1e-2, False)])
 def test_mu_floor(mu_rel, floor_active):
     # mu_eff = max(mu, mu_floor * max diag): the step taken is the one damped by mu_eff

@@ -1372,9 +1372,10 @@ __device__ __forceinline__ double reduce4(double v, double* sh) {
 // solve position D on) accumulate the contributions of all blocks at distance >= D as their
 // solutions appear and hand the 64-entry partial sum to the worker, which has D-1 steps of
 // slack (D = chain_d<R> = 3: the worker streams D tiles per step through its one compute
-// unit, so a larger D slows every step, and a smaller one leaves the hand-off too little).  In the worker the four 16-column parts of a row sit
-// in adjacent lanes of one wave, so a row sum is two DPP exchanges in a fixed order and a
-// step needs two workgroup barriers.
+// unit, so a larger D slows every step, and a smaller one leaves the hand-off too little
+// slack).  In the worker the four 16-column parts of a row sit in adjacent lanes of one
+// wave, so a row sum is two DPP exchanges in a fixed order and a step needs two workgroup
+// barriers.
 // Hand-offs carry the data itself: solution blocks and partial sums travel through two
 // message arrays written and read with agent-scope relaxed 64-bit atomics, and a slot that
 // still holds kEmpty (a signalling-NaN payload that no arithmetic result carries) is not

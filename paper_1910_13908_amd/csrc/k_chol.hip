@@ -32,10 +32,10 @@
 // The factor is stored tile-packed (column-major over the tiles of the lower triangle,
 // row-major inside a tile while it is built; after the factorisation k_transpose_tiles
 // rewrites every tile in the solves' layout and writes their transposed copies) next to the
-// inverses of the diagonal tiles, which the triangular solves use as small dense products.  Forward and backward substitution use the
-// same ticket scheme over 64-row blocks, with message hand-offs.  In mixed precision the
-// factor and the products run in FP32 (FP32 MFMA); right-hand sides, solutions and the
-// refinement residual g - (H + mu I) d are FP64.
+// inverses of the diagonal tiles, which the triangular solves use as small dense products.
+// Forward and backward substitution use the same ticket scheme over 64-row blocks, with
+// message hand-offs.  In mixed precision the factor and the products run in FP32 (FP32
+// MFMA); right-hand sides, solutions and the refinement residual g - (H + mu I) d are FP64.
 #include "common.h"
 
 #include <type_traits>
@@ -844,7 +844,8 @@ __device__ bool tagged_get16(const uint64_t* t, uint32_t seq, F elem, float (&v)
     __builtin_amdgcn_s_sleep(2);
   }
 }
-// The tile_fetch layout (thread t holds elements 4 (t + 256 i) .. + 3, i = 0..3) from a tagged tile.
+// The tile_fetch layout (thread t holds elements 4 (t + 256 i) .. + 3, i = 0..3) from a
+// tagged tile.
 __device__ __forceinline__ bool tagged_tile_fetch(const uint64_t* t, uint32_t seq,
                                                   TileRegs<float>& r, SyncArea* sync,
                                                   int32_t* status) {

@@ -33,3 +33,27 @@ def test_binding_round_trips_layouts():
     J = rng.normal(size=(3, 7, 2, 2)) + 1j * rng.normal(size=(3, 7, 2, 2))
     assert np.array_equal(ddcal.jones_complex(ddcal.jones_real(J)), J)
     assert ddcal.planes(x)[0, 1, 2, 3, 4] == x[0, 2, 3, 4, 0, 0].imag
+
+
+def test_binding_without_the_library_raises(tmp_path):
+    # the package's Python files without libddcal.so: importing the binding fails loudly
+    import shutil
+    import subprocess
+    import sys
+    pkg = tmp_path / "paper_1910_13908_amd"
+    pkg.mkdir()
+    for f in ("__init__.py", "ddcal.py", "synth.py"):
+        shutil.copy(os.path.join(ROOT, "paper_1910_13908_amd", f), pkg / f)
+    r = subprocess.run([sys.executable, "-c", "import paper_1910_13908_amd.ddcal"],
+                       cwd=tmp_path, capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "libddcal.so is missing" in r.stderr
+
+
+def test_the_package_never_reaches_the_oracle():
+    # only the tests, smoke() and the benchmark's CPU baseline may use oracle/
+    pkg = os.path.join(ROOT, "paper_1910_13908_amd")
+    for f in sorted(os.listdir(pkg)):
+        if f.endswith(".py"):
+            src = open(os.path.join(pkg, f)).read()
+            assert not re.search(r"^\s*(from|import)\s+oracle\b", src, flags=re.M), f

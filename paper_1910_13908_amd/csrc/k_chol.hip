@@ -94,17 +94,6 @@ __device__ __forceinline__ uint32_t tile_index(int I, int J, int T) {
   return (uint32_t)(J * T - (J * (J - 1)) / 2 + (I - J));
 }
 
-__device__ __forceinline__ void decode_ticket(uint32_t t, int T, int& I, int& J) {
-  int j = 0;
-  uint32_t start = 0;
-  while (start + (uint32_t)(T - j) <= t) {
-    start += (uint32_t)(T - j);
-    ++j;
-  }
-  J = j;
-  I = j + (int)(t - start);
-}
-
 // Wait until *flag != 0 (thread 0 polls; the workgroup then acquires).  Returns false on
 // abort or timeout.
 __device__ bool wait_flag(const uint32_t* flag, SyncArea* sync, int32_t* status) {

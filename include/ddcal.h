@@ -180,7 +180,8 @@ ddc_status ddc_residual(ddc_ctx* ctx, const ddc_obs* obs, int32_t n_clusters, co
 
 /* ddc_residual for callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same arguments,
- * kernels and results, bit for bit, with the call's scratch (canonical baseline table and
+ * arithmetic and results, bit for bit (the Jones matrices are read in place, not from
+ * component planes), with the call's scratch (canonical baseline table and
  * per-workgroup cost partials, 1.5 MiB) in a fixed device array that each GPU holds for the
  * life of the process, instead of the context workspace.  The call allocates nothing
  * (no hipMalloc/hipFree, no workspace growth).  Limits: n_stations <= 512 and

@@ -2,8 +2,9 @@
 
 TEST INFRASTRUCTURE ONLY.  Nothing on the product path imports, calls or links this
 package: only ``tests/``, ``__graft_entry__.smoke()`` and the host-time lines of ``bench.py``
-(the ``cpu_baseline`` leg and the oracle column of the scaling scan) may use it.  It shares no code with the HIP library; both sides read the same
-seeded draws from :mod:`paper_1910_13908_amd.synth`, which holds no calibration arithmetic.
+(the ``cpu_baseline`` leg and the oracle column of the scaling scan) may use it.  It shares
+no code with the HIP library; both sides read the same seeded draws from
+:mod:`paper_1910_13908_amd.synth`, which holds no calibration arithmetic.
 
 What it computes (NumPy, float64 / complex128 throughout):
 
